@@ -1,0 +1,165 @@
+"""Throughput benchmark of the batched reversible-jump photon-path sampler.
+
+Workload: 65,536 chains in 256 groups of 256 (one source/sensor pair and one
+homogeneous medium per group: scattering length log-U[10,50] m, absorption
+length log-U[50,200] m, g ~ U[0.8,0.95], sensor radius 0.165 m at U[5,100] m),
+vertex cap 256, FP32 evaluation with FP64 statistics; synthetic seeded inputs.
+
+One benchmark step = one pass of the hot path over the batch:
+  rjpath_run_chains (1000 sampler steps for every chain: perturbation /
+  birth / death proposals, local log-density, accept, statistics)
+  + rjpath_intensity (anchor quadrature, reduction, jackknife)
+  + rjpath_grad (score pass over every path).
+The default 10 timed steps after 1 warm-up step are the workload's 10^4
+sampler steps per chain with a 10% burn-in.
+
+Prints one JSON line: path-density evaluations per second (one evaluation =
+one proposal's log-density change, accepted or not), plus ESS/s of the
+detected intensity at 1% error, the roofline of the step kernel and the FP64
+oracle timed on the host cores on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32 = 157.3e12  # MI355X published dense FP32 vector rate (FLOP/s)
+
+# Algorithmic FP32 work per proposal (FLOPs, FMA = 2, one transcendental = 1),
+# counted from the arithmetic of the method ("Roofline"):
+FLOP_PERTURB = 217.0        # Gaussian step + two segments + three turns, old and new
+FLOP_JUMP_BASE = 208.0      # mean of birth (235) and death (180): proposal, segments, turns, Jacobian
+FLOP_JUMP_PER_VERTEX = 1.0  # birth scan of the cached depths (2 per vertex over half the path, half the jumps)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--chunk", type=int, default=1000, help="sampler steps per benchmark step")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def cpu_baseline(w, budget_s):
+    """The FP64 oracle, as it stands, on a bounded sample of the workload:
+    the first chain of every 16th chain group, sampler steps until ~budget_s."""
+    from oracle import oracle as O
+    idx = np.arange(0, len(w["c_target"]), 256 * 16)
+    ws = dict(w)
+    ws["c_target"] = np.asarray(w["c_target"])[idx]
+    orc = O.Oracle(ws)
+    st = O.initial_state(ws)
+    threads = os.cpu_count() or 1
+    steps, done, t_used = 200, 0, 0.0
+    while t_used < budget_s:
+        t0 = time.perf_counter()
+        orc.run(ws, st, steps, step0=done, threads=threads)
+        dt = time.perf_counter() - t0
+        t_used += dt
+        done += steps
+        if dt < budget_s / 8:
+            steps *= 2
+    evals = len(idx) * done
+    return dict(value=evals / t_used, unit="path-density evals/s", cores=min(threads, len(idx)), kind="oracle",
+                sample=f"{len(idx)} chains (one per 16 chain groups) x {done} steps, FP64, {t_used:.1f} s")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (each GPU would run its own share "
+              "of the chains; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1811_04156_amd import workloads as W
+    from paper_1811_04156_amd.rjpath import Sampler
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    w = W.config2()
+    w["burn_in"] = args.warmup * args.chunk
+    s = Sampler(w, device="cuda:0", precision="f32")
+    stream = torch.cuda.current_stream()
+    C = s.C
+    # warm-up (burn-in) steps, untimed
+    for _ in range(args.warmup):
+        s.run(args.chunk)
+        s.intensity()
+        s.grad(logp=False, score=True)
+    torch.cuda.synchronize()
+    k_ms = []
+    n_mean = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        s.run(args.chunk)
+        e1.record(stream)
+        res = s.intensity()
+        s.grad(logp=False, score=True)
+        k_ms.append((e0, e1))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    kern = [a.elapsed_time(b) for a, b in k_ms]
+    sampler_steps = args.steps * args.chunk
+    evals = C * sampler_steps
+    value = evals / wall
+    # ESS/s of the detected intensity at 1% relative error (median target)
+    r = res["se"] / res["I"]
+    ok = np.isfinite(r) & (r > 0)
+    r_med = float(np.median(r[ok])) if ok.any() else float("nan")
+    t_sampling = wall  # statistics accumulate over the timed steps only (burn-in excluded)
+    t1pct = t_sampling * (r_med / 0.01) ** 2
+    ess_s = 1e4 / t1pct
+    # roofline of the step kernel: algorithmic FLOPs per launch / mean launch time
+    stats = s.stats.cpu().numpy()
+    nbar = stats[:, 5].sum() / max(1.0, stats[:, 0].sum())
+    mix_p = w["n_perturb"] / w["cycle_len"]
+    flop_per_prop = mix_p * FLOP_PERTURB + (1 - mix_p) * (FLOP_JUMP_BASE + FLOP_JUMP_PER_VERTEX * nbar)
+    flop_launch = flop_per_prop * C * args.chunk
+    k_mean = float(np.mean(kern)) * 1e-3
+    achieved = flop_launch / k_mean
+    acc = stats[:, 9:12].sum(0) / np.maximum(1, stats[:, 6:9].sum(0))
+    out = {
+        "metric": "path-density evals/s + ESS/s of detected intensity at 1% err, grad vs plain",
+        "value": value,
+        "unit": "path-density evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "batched plain RJMCMC, 65,536 chains x 256 homogeneous groups, cap 256, "
+                               "1e4 sampler steps (1e3 per bench step), FP32 eval / FP64 stats",
+                   "chains": C, "sampler_steps_per_bench_step": args.chunk, "cap": int(w["cap"])},
+        "ess_per_s": ess_s,
+        "t_1pct_s": t1pct,
+        "median_rel_err": r_med,
+        "mean_vertices": nbar,
+        "acceptance": {"perturb": acc[0], "birth": acc[1], "death": acc[2]},
+        "kernel_ms_per_launch": float(np.mean(kern)),
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32, "traffic": None},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,260 @@
+/*
+ * rjpath.h -- C ABI of librjpath.so: batched reversible-jump MCMC sampling of
+ * photon paths from a point source to a spherical light sensor through a
+ * scattering and absorbing medium, on AMD Instinct MI355X (gfx950).
+ *
+ * Method: G. H. Collin, "Using path integrals for the propagation of light in
+ * a scattering dominated medium", arXiv:1811.04156.  A path is a polyline
+ * f_0 .. f_{n-1} (Sec. "Numerical path integration"); its density is the
+ * factorised product of the appendix ("Path probability distribution"):
+ *   p = p_i(f_0,f_1) prod_{k=1}^{n-2} p_v(f_{k-1},f_k,f_{k+1}) p_f(f_{n-2},f_{n-1}).
+ * Chains move by single-vertex perturbations and by birth/death jumps through
+ * the bi-spherical dimension-matching map (App. "Jump proposal", "Dimension
+ * matching transformation"), accepted with Green's reversible-jump ratio
+ * (eq. acceptFact).  The detected intensity is the integral of p over all
+ * paths (Sec. "Comparison of relative light yield" motivates it; the
+ * estimator used here anchors one sector by quadrature).
+ *
+ * Conventions shared by every call:
+ *  - Every array argument marked "device" is a device pointer owned by the
+ *    caller; "host" arrays are read during the call only.  The library owns
+ *    only the opaque rjpath_medium handle and the workspaces inside it.
+ *  - Calls return RJPATH_OK (0) or a negative error code; they never throw.
+ *    rjpath_last_error() returns a thread-local message for the last failure.
+ *    Argument errors are detected on the host before any work is enqueued.
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream).
+ *    rjpath_run_chains and rjpath_grad are asynchronous; rjpath_intensity
+ *    synchronises the stream because its finalisation runs on the host.
+ *  - Lengths are metres.  Media are given as scattering length lambda_s and
+ *    absorption length lambda_a (b = 1/lambda_s, a = 1/lambda_a; an infinite
+ *    length means a zero coefficient) and the mean scattering cosine g.
+ */
+#ifndef RJPATH_H
+#define RJPATH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    RJPATH_OK = 0,
+    RJPATH_EINVAL = -1,  /* invalid argument (message says which) */
+    RJPATH_ENOMEM = -2,  /* device allocation failed (init / workspace growth only) */
+    RJPATH_EHIP = -3,    /* a HIP runtime call failed (message has the HIP error) */
+    RJPATH_ENODATA = -4, /* a target has no anchor-sector visits yet */
+    RJPATH_ENOTSUP = -5  /* combination not supported by this build */
+};
+
+enum { RJPATH_F32 = 0, RJPATH_F64 = 1 };              /* element type of path vertices */
+enum { RJPATH_PLAIN = 0, RJPATH_MALA = 1 };           /* interior-vertex move */
+enum { RJPATH_EMIT_ISO = 0, RJPATH_EMIT_VMF = 1, RJPATH_EMIT_CONE = 2 };
+enum { RJPATH_DET_UNIFORM = 0, RJPATH_DET_PAPER = 1 };
+
+/* Per-chain statistics, RJPATH_NSTAT doubles per chain, added to by every
+ * post-burn-in step (step index >= burn_in):
+ *  0 samples              1 sum 1/w(n)             2 sum [n == n0] / w(n0)
+ *  3 sum path length L    4 sum L^2                 5 sum n
+ *  6 proposed perturb     7 proposed birth          8 proposed death
+ *  9 accepted perturb    10 accepted birth         11 accepted death
+ * 12 steps at n == cap   13 proposed MALA          14 accepted MALA
+ * 15 reserved (0)                                                         */
+enum { RJPATH_NSTAT = 16 };
+
+/* Per-step trace record (tests): 5 doubles per chain and step:
+ * move (0 interior, 1 end point, 2 birth, 3 death, 4 MALA, 5 none),
+ * accepted (0/1), index (vertex or segment, -1 if none), log A, log u. */
+enum { RJPATH_TRACE_WORDS = 5 };
+
+typedef struct rjpath_medium rjpath_medium;
+
+/* Layered media (App. "Intermediate vertex": a(x), b(x), sigma(cos theta)).
+ * Medium m has layer_cnt[m] layers along the unit axis axis[3m..3m+2];
+ * its edges are edges[layer_off[m] + m .. layer_off[m] + m + layer_cnt[m]]
+ * (strictly increasing), layer l covers [edge_l, edge_{l+1}) and the first and
+ * last layers extend to -inf / +inf.  Per-layer arrays are indexed by
+ * layer_off[m] + l.  f_sl is the simplified-Liu fraction of the scattering
+ * function (eq. angular_scattering); 0 gives pure Henyey-Greenstein.
+ * All arrays are host memory. */
+typedef struct {
+    int32_t n_media;
+    const double* axis;
+    const int32_t* layer_off;
+    const int32_t* layer_cnt;
+    const double* edges;
+    const double* lam_s;
+    const double* lam_a;
+    const double* g;
+    const double* f_sl;
+} rjpath_medium_desc;
+
+/* Source/sensor pairs ("targets"); every array is device memory, T entries.
+ *  medium[T]       medium index
+ *  src[3T]         absolute point-source position (App. "Initial vertex")
+ *  sensor[3T]      absolute centre of the spherical sensor (App. "Final vertex")
+ *  radius[T]       sensor radius
+ *  emit_kind[T]    RJPATH_EMIT_*: isotropic; von Mises-Fisher (eq. emission_dist,
+ *                  emit_param = kappa); uniform cone (emit_param = half-angle, rad)
+ *  emit_dir[3T]    preferred emission direction (unit)
+ *  emit_param[T]
+ *  det_kind[T]     RJPATH_DET_*: rho = 1, or eq. (detection_prob) with det_dir
+ *  det_dir[3T]     preferred sensor direction rho_hat (unit)
+ *  n0[T]           anchor sector (2 or 3) of the intensity estimator
+ *  logw            NULL, or T*(cap+1) sector tilts log w(n) (the chain samples
+ *                  p(f) w(n); the intensity estimator undoes the tilt)       */
+typedef struct {
+    int32_t n_targets;
+    const int32_t* medium;
+    const double* src;
+    const double* sensor;
+    const double* radius;
+    const int32_t* emit_kind;
+    const double* emit_dir;
+    const double* emit_param;
+    const int32_t* det_kind;
+    const double* det_dir;
+    const int32_t* n0;
+    const double* logw;
+} rjpath_targets;
+
+/* Chain state, all device memory.  Vertex v of chain c is element
+ * verts[v * n_chains + c], four values (x, y, z, w) of the precision's type:
+ * x, y, z relative to the chain's source (f_0 = 0), w is library-owned scratch
+ * (the scattering depth of the segment leaving the vertex).  Slots v >= n[c]
+ * are unused.  logp[c] receives log p of the final path; status[c] is 0 for a
+ * healthy chain and 1 if its starting path had zero or non-finite density
+ * (such a chain is not moved and adds nothing to the statistics).
+ * work: MALA proposal buffer with the layout of verts (required only for
+ * RJPATH_MALA, else may be NULL). */
+typedef struct {
+    int32_t n_chains;
+    int32_t cap;       /* maximum vertex count, 2 <= cap <= 4096 */
+    int32_t precision; /* RJPATH_F32 or RJPATH_F64 */
+    const int32_t* target;
+    int32_t* n;
+    void* verts;
+    double* logp;
+    int32_t* status;
+    double* stats; /* n_chains * RJPATH_NSTAT */
+    void* work;
+} rjpath_chains;
+
+/* Run parameters.  The random draws of chain c at global step s are two
+ * Philox4x32-10 blocks with counter (c, s mod 2^32, s >> 32, 0 / 1) and key
+ * (seed mod 2^32, seed >> 32); MALA vertex k uses counter word 3 = 2 + k.
+ * Step s is a perturbation step if (s mod cycle_len) < n_perturb, else a jump
+ * step that is a birth when draw 2 < birth_thresh and a death otherwise
+ * (birth_thresh = birth fraction * 2^32).  Steps run from step0 to
+ * step0 + steps - 1; statistics accumulate for steps >= burn_in.
+ * sigma: standard deviation (m) of the Gaussian interior-vertex step;
+ * kappa_end: concentration of the von Mises-Fisher end-point step on the
+ * sensor; sampler: RJPATH_PLAIN or RJPATH_MALA (interior steps become joint
+ * Langevin moves of all interior vertices with step size mala_h, m^2).
+ * block_chains (multiple of 64) and v_lds (vertex slots per chain kept in
+ * LDS) select the launch; 0 takes the values tuned for this handle (see
+ * rjpath_autotune) or a default.  chunk: steps per kernel launch (0 = all).
+ * trace: NULL or n_chains * steps * RJPATH_TRACE_WORDS doubles.
+ * hist: NULL or n_targets * (cap + 1) uint32 counts of the sector n after
+ * every post-burn-in step (for tuning the sector tilt). */
+typedef struct {
+    uint64_t seed;
+    uint64_t step0;
+    int64_t burn_in;
+    int32_t steps;
+    int32_t cycle_len;
+    int32_t n_perturb;
+    uint32_t birth_thresh;
+    double sigma;
+    double kappa_end;
+    int32_t sampler;
+    double mala_h;
+    int32_t block_chains;
+    int32_t v_lds;
+    int32_t chunk;
+    double* trace;
+    uint32_t* hist;
+} rjpath_run_params;
+
+/* Thread-local description of the last error. */
+const char* rjpath_last_error(void);
+
+/* Library version string. */
+const char* rjpath_version(void);
+
+/* Builds the device tables of one or more layered media (per layer: a, b,
+ * log b, Henyey-Greenstein and simplified-Liu constants, the concentration
+ * kappa_eq with coth(k) - 1/k = g of the birth centering rule (App. "Dimension
+ * matching transformation"), prefix integrals of a and b along the axis).
+ * Allocates device memory (the only call besides rjpath_autotune that does).
+ * Errors: RJPATH_EINVAL for n_media < 1, an empty medium, lambda <= 0 or NaN,
+ * |g| >= 1, f_sl outside [0,1], unsorted edges or a non-unit axis. */
+int rjpath_init_medium(rjpath_medium** out, const rjpath_medium_desc* desc, void* stream);
+
+/* Releases the handle and its device memory (NULL is a no-op). */
+int rjpath_free_medium(rjpath_medium* m);
+
+/* Advances every chain by p->steps reversible-jump steps in place and adds
+ * the per-chain statistics (see RJPATH_NSTAT) into c->stats.  Deterministic
+ * given (seed, step0): the same state and parameters give bit-identical
+ * results for any launch configuration.  Paths are clamped to n <= cap (a
+ * birth at cap is a rejected proposal).  Allocates nothing. */
+int rjpath_run_chains(rjpath_medium* m, const rjpath_targets* t, const rjpath_chains* c,
+                      const rjpath_run_params* p, void* stream);
+
+/* Anchor integrals I_{n0} per target (host output, T doubles): the integral
+ * of p over the anchor sector, by product Gauss quadrature on the device in
+ * FP64.  n0 = 2: over the directions from the source into the sensor
+ * (dOmega = cos Phi dA / r^2, App. "Final vertex"); n0 = 3: one scattering
+ * vertex, integrated over emission directions and, along each ray, layer by
+ * layer between the layer edges it crosses.  Independent of the chains; the
+ * result can be reused while media and targets are unchanged.
+ * Synchronises `stream`; may grow a workspace inside the handle. */
+int rjpath_anchor(rjpath_medium* m, const rjpath_targets* t, double* anchor, void* stream);
+
+/* Detected intensity per target from the chain statistics, with the anchored
+ * sector estimator  I = I_{n0} * sum_c stats[1] / sum_c stats[2].
+ * anchor: host array of the T anchors from rjpath_anchor, or NULL to have
+ * them computed in this call.  Standard error by delete-one-group jackknife
+ * over `groups` chain groups of each target (a chain's group is a hash of
+ * its index; 2 <= groups <= 64).  Host outputs (each T doubles, any may be
+ * NULL): I, se, ess = (I/se)^2, rhat = potential scale reduction of the path
+ * length over the groups (Sec. "Implementation").  Synchronises `stream`;
+ * may grow a workspace inside the handle.
+ * Errors: RJPATH_ENODATA if a target with chains has no anchor-sector
+ * visits (its outputs are NaN; the others are still written). */
+int rjpath_intensity(rjpath_medium* m, const rjpath_targets* t, const rjpath_chains* c, int32_t groups,
+                     const double* anchor, double* I, double* se, double* ess, double* rhat, void* stream);
+
+/* Score of the current paths, recomputed from the vertices (no stored tape):
+ *  logp_out[C]      (device, may be NULL): log p of each path, FP64 sum
+ *  dlogp_dv         (device, may be NULL): d log p / d vertex, layout of verts,
+ *                   precision of the chains; w component 0; vertex 0 gets 0
+ *  score            (device, may be NULL): n_targets * (1 + 3 * L_total)
+ *                   doubles ADDED to: [t][0] += sum_c 1/w(n_c) and
+ *                   [t][1 + 3 l + k] += sum_c (1/w(n_c)) d log p / d theta_{l,k}
+ *                   for global layer index l and theta = (lambda_s, lambda_a, g),
+ *                   over the chains of target t with status 0.
+ * Since I = int p, d log I / d theta = E_p[d log p / d theta] = score[t][1+..] / score[t][0]
+ * averaged over samples (App. "Path probability distribution" gives log p). */
+int rjpath_grad(rjpath_medium* m, const rjpath_targets* t, const rjpath_chains* c, double* logp_out,
+                void* dlogp_dv, double* score, void* stream);
+
+/* Times short launches of rjpath_run_chains over the candidate launch
+ * configurations (chains per block in {64, 128, 256} x LDS vertex slots in
+ * {4, 8, 12, 16, 24, 32, 48, 64}, capped at cap and at 160 KiB of LDS) on the
+ * given chains, advancing them by exactly `steps` steps starting at p->step0
+ * (ordinary sampler steps, so they may serve as burn-in: the chain trajectory
+ * does not depend on the launch configuration), and stores the fastest
+ * configuration in the handle for this (cap, precision, sampler).  Writes it to
+ * best_block_chains / best_v_lds if non-NULL.  `steps` must be at least the
+ * number of candidates.  Synchronises the stream. */
+int rjpath_autotune(rjpath_medium* m, const rjpath_targets* t, const rjpath_chains* c,
+                    const rjpath_run_params* p, int32_t steps, int32_t* best_block_chains, int32_t* best_v_lds,
+                    void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RJPATH_H */

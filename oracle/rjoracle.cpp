@@ -708,9 +708,7 @@ double anchor_I3(const Ctx& cx, const Target& t, int nth, int nps, int nr, int n
     std::vector<double> tx, tw, rx, rw;
     gauss_legendre(nth, tx, tw);
     gauss_legendre(nr, rx, rw);
-    double cref = INFINITY; // reference attenuation for the distance map
-    for (int l = 0; l < m.L; ++l) cref = std::min(cref, m.a[l] + m.b[l]);
-    cref = std::min(cref, 1.0 / norm(t.eta));
+    const double u0 = axis_coord(cx, t, V3{0, 0, 0});
     double sum = 0;
     for (int i = 0; i < nth; ++i) {
         double c0 = 0.5 * (1 - cmax) * tx[i] + 0.5 * (1 + cmax); // cos polar in [cmax, 1]
@@ -721,16 +719,46 @@ double anchor_I3(const Ctx& cx, const Target& t, int nth, int nps, int nr, int n
             V3 w0 = c0 * ax + s0 * (std::cos(ps) * e2 + std::sin(ps) * e3);
             double eps = emission(t, w0);
             if (!(eps > 0)) continue;
-            for (int q = 0; q < nr; ++q) {
-                double x = 0.5 * (rx[q] + 1), wx = 0.5 * rw[q];
-                double r = -std::log1p(-x) / cref, drdx = 1.0 / (cref * (1 - x));
-                V3 f1 = r * w0;
-                int l = layer_of(m, axis_coord(cx, t, f1));
-                double tau = depth(m, m.a, axis_coord(cx, t, V3{0, 0, 0}), axis_coord(cx, t, f1), r) +
-                             depth(m, m.b, axis_coord(cx, t, V3{0, 0, 0}), axis_coord(cx, t, f1), r);
-                if (norm(t.eta - f1) <= t.R * 1.0000001) continue;
-                double K = cap_integral(cx, t, f1, nv, npsi, [&](V3 u) { return sigma_sr(dot(w0, u), m.g[l], m.fsl[l]); });
-                sum += wc * (2 * PI / nps) * wx * drdx * eps * std::exp(-tau) * m.b[l] * K;
+            // The radial integrand jumps with b(x) and kinks with tau where the
+            // ray crosses a layer edge: integrate piece by piece between the
+            // crossings; the last, unbounded piece uses r = r_m - log(1-x)/c_m,
+            // which maps its exponential attenuation onto [0, 1).
+            double du = dot(m.axis, w0);
+            std::vector<double> br{0.0};
+            if (du != 0)
+                for (int k = 1; k < m.L; ++k) {
+                    double rk = (m.edge[k] - u0) / du;
+                    if (rk > 0) br.push_back(rk);
+                }
+            std::sort(br.begin(), br.end());
+            for (size_t pc = 0; pc < br.size(); ++pc) {
+                double a = br[pc];
+                if (depth(m, m.a, u0, u0 + du * a, a) + depth(m, m.b, u0, u0 + du * a, a) > 60) break;
+                bool last = pc + 1 == br.size();
+                int lpc = layer_of(m, u0 + du * (last ? a + 1.0 : 0.5 * (a + br[pc + 1])));
+                double cm = m.a[lpc] + m.b[lpc];
+                for (int q = 0; q < nr; ++q) {
+                    double x = 0.5 * (rx[q] + 1), wx = 0.5 * rw[q], r, drdx;
+                    if (!last) {
+                        r = a + (br[pc + 1] - a) * x;
+                        drdx = br[pc + 1] - a;
+                    } else if (cm > 0) {
+                        r = a - std::log1p(-x) / cm;
+                        drdx = 1.0 / (cm * (1 - x));
+                    } else {
+                        double L0 = norm(t.eta);
+                        r = a + L0 * x / (1 - x);
+                        drdx = L0 / ((1 - x) * (1 - x));
+                    }
+                    V3 f1 = r * w0;
+                    if (norm(t.eta - f1) <= t.R * 1.0000001) continue;
+                    int l = layer_of(m, axis_coord(cx, t, f1));
+                    double uf = axis_coord(cx, t, f1);
+                    double tau = depth(m, m.a, u0, uf, r) + depth(m, m.b, u0, uf, r);
+                    double K = cap_integral(cx, t, f1, nv, npsi,
+                                            [&](V3 u) { return sigma_sr(dot(w0, u), m.g[l], m.fsl[l]); });
+                    sum += wc * (2 * PI / nps) * wx * drdx * eps * std::exp(-tau) * m.b[l] * K;
+                }
             }
         }
     }

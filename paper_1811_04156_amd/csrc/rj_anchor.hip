@@ -1,0 +1,233 @@
+// rj_anchor.hip -- the anchor-sector integrals of the intensity estimator
+// and the per-target reduction of the chain statistics.
+//
+// The chains sample p(f) w(n) up to its normalisation; the integral of p over
+// one sector n0 is computed here by deterministic quadrature, so that
+// I = I_{n0} * E[1/w(n)] / E[1(n = n0) / w(n0)].
+//   n0 = 2: I_2 = int over directions u from the source into the sensor of
+//           eps(u) e^{-tau(hit)} rho(nu) dOmega  (dOmega = cos Phi dA / r^2,
+//           App. "Final vertex").
+//   n0 = 3: I_3 = int dOmega_0 eps(w0) int dr e^{-tau(0 -> r w0)} b(r w0) K(r w0),
+//           K = int over directions into the sensor from r w0 of
+//               sigma_sr(w0 . u) e^{-tau} rho dOmega  (d^3 f = r^2 dr dOmega_0
+//           cancels the 1/|r|^2 of the first segment; App. "Intermediate vertex").
+// Emission directions are parametrised by the inverse CDF of eps, which
+// absorbs eps into the measure; sensor directions by
+// v = sqrt(R^2 - D^2 sin^2 theta) / R (smooth at the cap rim).
+#include <hip/hip_runtime.h>
+
+#include "rj_device.h"
+#include "rj_kernels.h"
+
+namespace rj {
+
+namespace {
+
+const double PI = 3.14159265358979323846;
+
+__device__ double log_rho(const Tgt<double>& T, V3<double> nu) {
+    if (T.dk != RJPATH_DET_PAPER) return 0.0;
+    double cr = dot(nu, T.dd);
+    return 3 * cr - 1 - log(cosh(2 * cr + 0.7));
+}
+
+__device__ void frame(V3<double> ax, V3<double>& e2, V3<double>& e3) { onb(ax, e2, e3); }
+
+__device__ double depth_c(const Tgt<double>& T, V3<double> P, V3<double> Q) {
+    V3<double> r = Q - P;
+    double len = sqrt(dot(r, r)), tc, tb;
+    seg_depth(T, P, Q, len, tc, tb);
+    return tc;
+}
+
+// int over directions from P into the sensor of wfun(u) e^{-tau} rho dOmega
+template <class W>
+__device__ double cap_quad(const Tgt<double>& T, V3<double> P, const double* gx, const double* gw, int nv, int npsi,
+                           W wfun) {
+    V3<double> dv = T.eta - P;
+    double D = sqrt(dot(dv, dv)), Rr = (double)T.rad;
+    if (!(D > Rr)) return 0.0;
+    V3<double> ax = (1.0 / D) * dv, e2, e3;
+    frame(ax, e2, e3);
+    double k2 = Rr * Rr / (D * D), sum = 0.0;
+    for (int i = 0; i < nv; ++i) {
+        double v = gx[i], wv = gw[i];
+        double s2 = k2 * (1 - v * v);
+        double ct = sqrt(1 - s2), st = sqrt(s2);
+        double len = D * ct - Rr * v;
+        double jac = k2 * v / ct;
+        for (int j = 0; j < npsi; ++j) {
+            double ps = 2 * PI * (j + 0.5) / npsi;
+            double sp, cp;
+            sincos(ps, &sp, &cp);
+            V3<double> u = ct * ax + st * (cp * e2 + sp * e3);
+            V3<double> hit = P + len * u;
+            V3<double> nu = (1.0 / Rr) * (hit - T.eta);
+            double lw = wfun(u);
+            if (lw == -__builtin_inf()) continue;
+            sum += wv * (2 * PI / npsi) * jac * exp(lw - depth_c(T, P, hit) + log_rho(T, nu));
+        }
+    }
+    return sum;
+}
+
+// direction of the emission inverse CDF at (x, psi); eps dOmega = dx dpsi / (2 pi)
+__device__ V3<double> emit_dir_icdf(const Tgt<double>& T, double x, double ps) {
+    V3<double> ax = T.ek == RJPATH_EMIT_ISO ? V3<double>{0, 0, 1} : T.ed, e2, e3;
+    frame(ax, e2, e3);
+    double c;
+    if (T.ek == RJPATH_EMIT_ISO) c = 1 - 2 * x;
+    else if (T.ek == RJPATH_EMIT_VMF) c = 1 + log(x + (1 - x) * exp(-2 * (double)T.kappa)) / (double)T.kappa;
+    else c = 1 - x * (1 - (double)T.ecos);
+    double s = sqrt(fmax(0.0, 1 - c * c)), sp, cp;
+    sincos(ps, &sp, &cp);
+    return c * ax + s * (cp * e2 + sp * e3);
+}
+
+__global__ void __launch_bounds__(256) anchor_kernel(KArgs a, const double* gx, const double* gw, int ngl,
+                                                     double* anchor) {
+    const int t = blockIdx.x;
+    // block-uniform guard: every thread of the block leaves together
+    if (a.medium[t] < 0 || a.medium[t] >= a.n_media || (a.n0[t] != 2 && a.n0[t] != 3)) {
+        if (threadIdx.x == 0) anchor[t] = __builtin_nan("");
+        return;
+    }
+    Tgt<double> T;
+    load_target<double>(a, t, T, MedTab<double>{a.lay64, a.edge, a.pre});
+    __shared__ double red[256];
+    double part = 0.0;
+    const int n0 = a.n0[t];
+    // Gauss-Legendre tables on [0,1]: rule k of size m_k at offset o_k
+    // (sizes 8, 16, 32, 64 stored back to back)
+    const double* x8 = gx;       const double* w8 = gw;
+    const double* x32 = gx + 24; const double* w32 = gw + 24;
+    const double* x64 = gx + 56; const double* w64 = gw + 56;
+    (void)ngl;
+    if (n0 == 2) {
+        // 64 x 64 product rule, one direction per thread-iteration
+        for (int i = threadIdx.x; i < 64 * 64; i += blockDim.x) {
+            int iv = i / 64, ip = i % 64;
+            V3<double> dv = T.eta;
+            double D = sqrt(dot(dv, dv)), Rr = (double)T.rad;
+            V3<double> ax = (1.0 / D) * dv, e2, e3;
+            frame(ax, e2, e3);
+            double k2 = Rr * Rr / (D * D);
+            double v = x64[iv], wv = w64[iv];
+            double s2 = k2 * (1 - v * v), ct = sqrt(1 - s2), st = sqrt(s2);
+            double len = D * ct - Rr * v, jac = k2 * v / ct;
+            double ps = 2 * PI * (ip + 0.5) / 64, sp, cp;
+            sincos(ps, &sp, &cp);
+            V3<double> u = ct * ax + st * (cp * e2 + sp * e3);
+            V3<double> hit = len * u;
+            V3<double> nu = (1.0 / Rr) * (hit - T.eta);
+            double le = emit_term(T, u);
+            if (le == -__builtin_inf()) continue;
+            V3<double> o = {0, 0, 0};
+            part += wv * (2 * PI / 64) * jac * exp(le - depth_c(T, o, hit) + log_rho(T, nu));
+        }
+    } else {
+        // outer: 32 (inverse-CDF polar) x 32 (azimuth) directions; along each
+        // ray, one 8-point Gauss rule per layer crossed (b jumps and tau kinks
+        // at the edges) and, past the last edge, the map r = a - log(1-x)/c
+        // that absorbs the exponential attenuation; inner 8 x 8 cap rule.
+        const int cnt = T.mcnt;
+        const double Dn = sqrt(dot(T.eta, T.eta));
+        for (int i = threadIdx.x; i < 32 * 32; i += blockDim.x) {
+            int ix = i / 32, ip = i % 32;
+            double x = x32[ix], wx = w32[ix];
+            double ps = 2 * PI * (ip + 0.5) / 32;
+            V3<double> w0 = emit_dir_icdf(T, x, ps);
+            double du = T.ax * w0.x + T.ay * w0.y + T.az * w0.z;
+            int l = layer_u(T, T.usrc);
+            double a = 0.0, taua = 0.0, ray = 0.0;
+            for (int guard = 0; guard <= cnt; ++guard) {
+                double bnd = 1e300;
+                int lnext = l;
+                if (du > 0 && l + 1 < cnt) {
+                    bnd = (T.edge[l + 1] - T.usrc) / du;
+                    lnext = l + 1;
+                } else if (du < 0 && l > 0) {
+                    bnd = (T.edge[l] - T.usrc) / du;
+                    lnext = l - 1;
+                }
+                const bool tail = !(bnd < 1e299);
+                const LayV<double> ly = lay_at(T, l);
+                const double cm = ly.c, bm = ly.b;
+                for (int q = 0; q < 8; ++q) {
+                    double y = x8[q], wy = w8[q], r, wr;
+                    if (!tail) {
+                        r = a + (bnd - a) * y;
+                        wr = wy * (bnd - a) * exp(-taua - cm * (r - a));
+                    } else if (cm > 0) {
+                        r = a - log1p(-y) / cm;
+                        wr = wy * exp(-taua) / cm;
+                    } else {
+                        r = a + Dn * y / (1 - y);
+                        wr = wy * Dn / ((1 - y) * (1 - y)) * exp(-taua);
+                    }
+                    if (!(bm > 0) || !(wr > 0)) continue;
+                    V3<double> f1 = r * w0;
+                    V3<double> df = T.eta - f1;
+                    if (dot(df, df) <= (double)T.rad * (double)T.rad * 1.0000002) continue;
+                    double K = cap_quad(T, f1, x8, w8, 8, 8, [&](V3<double> u) { return turn_term(ly, w0, u); });
+                    ray += wr * bm * K;
+                }
+                if (tail) break;
+                taua += cm * (bnd - a);
+                a = bnd;
+                l = lnext;
+                if (taua > 60.0) break;
+            }
+            part += wx * (1.0 / 32) * ray;
+        }
+    }
+    red[threadIdx.x] = part;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) anchor[t] = red[0];
+}
+
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {
+    // integer finaliser (MurmurHash3 fmix32) for interleaved chain groups
+    x ^= x >> 16;
+    x *= 0x85ebca6bu;
+    x ^= x >> 13;
+    x *= 0xc2b2ae35u;
+    x ^= x >> 16;
+    return x;
+}
+
+__global__ void __launch_bounds__(256) reduce_kernel(KArgs a, int groups, double* red) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.C || a.status[c] != 0) return;
+    const int t = a.target[c];
+    if (t < 0 || t >= a.T) return;
+    const int g = (int)(mix32((uint32_t)c) % (uint32_t)groups);
+    const double* s = a.stats + (size_t)c * RJPATH_NSTAT;
+    double* r = red + ((size_t)t * groups + g) * RD_NW;
+    atomicAdd(r + RD_SAMPLES, s[0]);
+    atomicAdd(r + RD_A, s[1]);
+    atomicAdd(r + RD_B, s[2]);
+    atomicAdd(r + RD_L, s[3]);
+    atomicAdd(r + RD_L2, s[4]);
+    atomicAdd(r + RD_CHAINS, 1.0);
+}
+
+} // namespace
+
+hipError_t launch_anchor(const KArgs& a, const double* gl_x, const double* gl_w, int ngl, double* anchor,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(anchor_kernel, dim3(a.T), dim3(256), 0, s, a, gl_x, gl_w, ngl, anchor);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(const KArgs& a, int groups, double* red, hipStream_t s) {
+    int block = 256, grid = (a.C + block - 1) / block;
+    hipLaunchKernelGGL(reduce_kernel, dim3(grid), dim3(block), 0, s, a, groups, red);
+    return hipGetLastError();
+}
+
+} // namespace rj

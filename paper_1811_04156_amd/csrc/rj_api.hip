@@ -1,0 +1,557 @@
+// rj_api.hip -- the C ABI of librjpath: argument checks, the medium tables,
+// launch selection and tuning, and the FP64 host finalisation of the
+// intensity estimator.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "rj_internal.h"
+#include "rj_kernels.h"
+
+using namespace rj;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(RJPATH_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(call, what)                                   \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) return hip_fail(e_, what);     \
+    } while (0)
+
+const double PI = 3.14159265358979323846;
+
+// coth(k) - 1/k = g, solved by bisection in FP64.
+double kappa_eq(double g) {
+    if (g <= 0) return 0.0;
+    double lo = 1e-9, hi = 1e6;
+    for (int i = 0; i < 300; ++i) {
+        double m = 0.5 * (lo + hi);
+        double f = 1.0 / std::tanh(m) - 1.0 / m;
+        (f < g ? lo : hi) = m;
+    }
+    return 0.5 * (lo + hi);
+}
+
+// n-point Gauss-Legendre rule mapped to [0, 1] (Newton iteration on P_n).
+void gl01(int n, double* x, double* w) {
+    for (int i = 0; i < n; ++i) {
+        double z = std::cos(PI * (i + 0.75) / (n + 0.5)), pp = 1;
+        for (int it = 0; it < 200; ++it) {
+            double p1 = 1, p2 = 0;
+            for (int k = 1; k <= n; ++k) {
+                double p3 = p2;
+                p2 = p1;
+                p1 = ((2.0 * k - 1) * z * p2 - (k - 1.0) * p3) / k;
+            }
+            pp = n * (z * p1 - p2) / (z * z - 1);
+            double dz = p1 / pp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-15) break;
+        }
+        x[i] = 0.5 * (1 - z);
+        w[i] = 1.0 / ((1 - z * z) * pp * pp);
+    }
+}
+
+struct TuneKey {
+    int cap, prec, sampler;
+    bool operator<(const TuneKey& o) const { return std::tie(cap, prec, sampler) < std::tie(o.cap, o.prec, o.sampler); }
+};
+
+} // namespace
+
+struct rjpath_medium {
+    int n_media = 0, L_total = 0, n_edges = 0;
+    bool layered = false; // some medium has more than one layer
+    MedInfo* d_info = nullptr;
+    double* d_edge = nullptr;
+    double* d_pre = nullptr;
+    float* d_lay32 = nullptr;
+    double* d_lay64 = nullptr;
+    double* d_gl = nullptr; // x (120) then w (120): rules of 8, 16, 32, 64 points
+    // intensity workspace
+    double* d_ws = nullptr;
+    size_t ws_bytes = 0;
+    std::map<TuneKey, std::pair<int, int>> tuned;
+};
+
+extern "C" {
+
+const char* rjpath_last_error(void) { return g_err.c_str(); }
+
+const char* rjpath_version(void) { return "rjpath 0.1 gfx950"; }
+
+int rjpath_init_medium(rjpath_medium** out, const rjpath_medium_desc* d, void* stream) {
+    if (!out || !d) return fail(RJPATH_EINVAL, "null argument");
+    *out = nullptr;
+    if (d->n_media < 1) return fail(RJPATH_EINVAL, "n_media must be >= 1");
+    if (!d->axis || !d->layer_off || !d->layer_cnt || !d->edges || !d->lam_s || !d->lam_a || !d->g || !d->f_sl)
+        return fail(RJPATH_EINVAL, "null medium array");
+    const int M = d->n_media;
+    int L = 0;
+    std::vector<MedInfo> info(M);
+    for (int m = 0; m < M; ++m) {
+        int off = d->layer_off[m], cnt = d->layer_cnt[m];
+        if (cnt < 1) return fail(RJPATH_EINVAL, "medium " + std::to_string(m) + " has no layer");
+        if (off != L) return fail(RJPATH_EINVAL, "layer_off must be the running sum of layer_cnt");
+        L += cnt;
+        const double* ax = d->axis + 3 * m;
+        double an = std::sqrt(ax[0] * ax[0] + ax[1] * ax[1] + ax[2] * ax[2]);
+        if (!(std::fabs(an - 1.0) < 1e-9)) return fail(RJPATH_EINVAL, "medium axis must be a unit vector");
+        const double* e = d->edges + off + m;
+        bool uni = true;
+        for (int l = 0; l < cnt; ++l) {
+            if (!(e[l + 1] > e[l])) return fail(RJPATH_EINVAL, "edges must be strictly increasing");
+        }
+        double h = (e[cnt] - e[0]) / cnt;
+        for (int l = 0; l <= cnt; ++l)
+            if (std::fabs(e[l] - (e[0] + l * h)) > 1e-9 * std::max(1.0, std::fabs(e[l]))) uni = false;
+        info[m] = MedInfo{off, cnt, uni ? 1 : 0, 0, ax[0], ax[1], ax[2], e[0], 1.0 / h};
+    }
+    std::vector<double> lay(L * LY_NW), edge(L + M), pre(2 * (L + M));
+    for (int l = 0; l < L; ++l) {
+        double ls = d->lam_s[l], la = d->lam_a[l], g = d->g[l], f = d->f_sl[l];
+        if (!(ls > 0) || !(la > 0)) return fail(RJPATH_EINVAL, "scattering and absorption lengths must be > 0");
+        if (!(std::fabs(g) < 1)) return fail(RJPATH_EINVAL, "|g| must be < 1");
+        if (!(f >= 0 && f <= 1)) return fail(RJPATH_EINVAL, "f_sl must lie in [0, 1]");
+        if (f > 0 && !(g > 0)) return fail(RJPATH_EINVAL, "the simplified-Liu term needs g > 0");
+        double a = std::isinf(la) ? 0.0 : 1.0 / la, b = std::isinf(ls) ? 0.0 : 1.0 / ls;
+        double* y = &lay[l * LY_NW];
+        y[LY_A] = a;
+        y[LY_B] = b;
+        y[LY_C] = a + b;
+        y[LY_LOGB] = b > 0 ? std::log(b) : -INFINITY;
+        y[LY_G] = g;
+        y[LY_HGN] = std::log((1 - g * g) / (4 * PI));
+        y[LY_HG1] = (1 - g) * (1 - g);
+        y[LY_KEQ] = kappa_eq(g);
+        y[LY_FSL] = f;
+        y[LY_SLN] = g > 0 ? std::log((1 + g) / (1 - g) / (4 * PI)) : 0.0;
+        y[LY_SLA] = g > 0 ? 2 * g / (1 - g) : 0.0;
+        y[LY_NW - 1] = 0.0;
+    }
+    for (int m = 0; m < M; ++m) {
+        int off = info[m].off, cnt = info[m].cnt;
+        const double* e = d->edges + off + m;
+        double pc = 0, pb = 0;
+        for (int l = 0; l <= cnt; ++l) {
+            edge[off + m + l] = e[l];
+            pre[2 * (off + m + l)] = pc;
+            pre[2 * (off + m + l) + 1] = pb;
+            if (l < cnt) {
+                pc += lay[(off + l) * LY_NW + LY_C] * (e[l + 1] - e[l]);
+                pb += lay[(off + l) * LY_NW + LY_B] * (e[l + 1] - e[l]);
+            }
+        }
+    }
+    std::vector<float> lay32(lay.begin(), lay.end());
+    std::vector<double> gl(240);
+    int o = 0;
+    for (int n : {8, 16, 32, 64}) {
+        gl01(n, &gl[o], &gl[120 + o]);
+        o += n;
+    }
+    rjpath_medium* h = new rjpath_medium;
+    h->n_media = M;
+    h->L_total = L;
+    h->n_edges = L + M;
+    for (int mi = 0; mi < M; ++mi) h->layered |= info[mi].cnt > 1;
+    hipStream_t s = (hipStream_t)stream;
+    auto up = [&](void** dst, const void* src, size_t bytes) -> hipError_t {
+        hipError_t e = hipMalloc(dst, bytes);
+        if (e != hipSuccess) return e;
+        e = hipMemcpyAsync(*dst, src, bytes, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return e;
+        return hipStreamSynchronize(s);
+    };
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = up((void**)&h->d_info, info.data(), sizeof(MedInfo) * M);
+    if (e == hipSuccess) e = up((void**)&h->d_edge, edge.data(), sizeof(double) * edge.size());
+    if (e == hipSuccess) e = up((void**)&h->d_pre, pre.data(), sizeof(double) * pre.size());
+    if (e == hipSuccess) e = up((void**)&h->d_lay32, lay32.data(), sizeof(float) * lay32.size());
+    if (e == hipSuccess) e = up((void**)&h->d_lay64, lay.data(), sizeof(double) * lay.size());
+    if (e == hipSuccess) e = up((void**)&h->d_gl, gl.data(), sizeof(double) * gl.size());
+    if (e == hipSuccess) e = set_run_lds_limit();
+    if (e != hipSuccess) {
+        rjpath_free_medium(h);
+        return hip_fail(e, "rjpath_init_medium");
+    }
+    *out = h;
+    return RJPATH_OK;
+}
+
+int rjpath_free_medium(rjpath_medium* h) {
+    if (!h) return RJPATH_OK;
+    hipFree(h->d_info);
+    hipFree(h->d_edge);
+    hipFree(h->d_pre);
+    hipFree(h->d_lay32);
+    hipFree(h->d_lay64);
+    hipFree(h->d_gl);
+    hipFree(h->d_ws);
+    delete h;
+    return RJPATH_OK;
+}
+
+} // extern "C"
+
+namespace {
+
+int check_targets(const rjpath_medium* m, const rjpath_targets* t) {
+    if (!m || !t) return fail(RJPATH_EINVAL, "null handle or targets");
+    if (t->n_targets < 1) return fail(RJPATH_EINVAL, "n_targets must be >= 1");
+    if (!t->medium || !t->src || !t->sensor || !t->radius || !t->emit_kind || !t->emit_dir || !t->emit_param ||
+        !t->det_kind || !t->det_dir || !t->n0)
+        return fail(RJPATH_EINVAL, "null target array");
+    return RJPATH_OK;
+}
+
+int grow_ws(rjpath_medium* m, size_t need) {
+    if (need <= m->ws_bytes) return RJPATH_OK;
+    if (m->d_ws) HIPCHK(hipFree(m->d_ws), "hipFree");
+    m->d_ws = nullptr;
+    m->ws_bytes = 0;
+    if (hipMalloc((void**)&m->d_ws, need) != hipSuccess) return fail(RJPATH_ENOMEM, "workspace allocation");
+    m->ws_bytes = need;
+    return RJPATH_OK;
+}
+
+int check_common(const rjpath_medium* m, const rjpath_targets* t, const rjpath_chains* c) {
+    int r = check_targets(m, t);
+    if (r) return r;
+    if (!c) return fail(RJPATH_EINVAL, "null chains");
+    if (c->n_chains < 1) return fail(RJPATH_EINVAL, "n_chains must be >= 1");
+    if (c->cap < 2 || c->cap > 4096) return fail(RJPATH_EINVAL, "cap must lie in [2, 4096]");
+    if (c->precision != RJPATH_F32 && c->precision != RJPATH_F64) return fail(RJPATH_EINVAL, "bad precision");
+    if (!c->target || !c->n || !c->verts || !c->logp || !c->status || !c->stats)
+        return fail(RJPATH_EINVAL, "null chain array");
+    return RJPATH_OK;
+}
+
+KArgs make_args(const rjpath_medium* m, const rjpath_targets* t, const rjpath_chains* c) {
+    KArgs a{};
+    if (!c) {
+        static const rjpath_chains none{};
+        c = &none;
+    }
+    a.C = c->n_chains;
+    a.cap = c->cap;
+    a.prec = c->precision;
+    a.target = c->target;
+    a.n = c->n;
+    a.verts = c->verts;
+    a.logp = c->logp;
+    a.status = c->status;
+    a.stats = c->stats;
+    a.work = c->work;
+    a.T = t->n_targets;
+    a.medium = t->medium;
+    a.src = t->src;
+    a.sensor = t->sensor;
+    a.radius = t->radius;
+    a.ek = t->emit_kind;
+    a.edir = t->emit_dir;
+    a.eparam = t->emit_param;
+    a.dk = t->det_kind;
+    a.ddir = t->det_dir;
+    a.n0 = t->n0;
+    a.logw = t->logw;
+    a.n_media = m->n_media;
+    a.minfo = m->d_info;
+    a.edge = m->d_edge;
+    a.pre = m->d_pre;
+    a.lay = c->precision == RJPATH_F64 ? (const void*)m->d_lay64 : (const void*)m->d_lay32;
+    a.lay64 = m->d_lay64;
+    a.L_total = m->L_total;
+    a.n_edges = m->n_edges;
+    a.tab_bytes = 0;
+    if (m->layered) {
+        // layer table, edges padded to an even count, prefix pairs (the run kernel's LDS layout)
+        size_t lay = ((size_t)m->L_total * LY_NW * (c->precision == RJPATH_F64 ? 8 : 4) + 15) & ~(size_t)15;
+        size_t bytes = lay + 8 * (((size_t)m->n_edges + 1) & ~(size_t)1) + 16 * (size_t)m->n_edges;
+        if (bytes <= 48 * 1024) a.tab_bytes = bytes;
+    }
+    return a;
+}
+
+size_t vtx_bytes(int prec) { return prec == RJPATH_F64 ? 32 : 16; }
+
+const size_t LDS_MAX = 160 * 1024;
+
+// LDS left for the per-lane vertex slots once the media tables are staged
+size_t slot_budget(const rjpath_medium* m, const rjpath_targets* t, const rjpath_chains* c) {
+    return LDS_MAX - make_args(m, t, c).tab_bytes;
+}
+
+void default_launch(int cap, int prec, int& block, int& V) {
+    block = 128;
+    int vmax = (64 * 1024) / (block * (int)vtx_bytes(prec));
+    V = std::min(cap, vmax);
+}
+
+int run_impl(rjpath_medium* m, const rjpath_targets* t, const rjpath_chains* c, const rjpath_run_params* p,
+             hipStream_t s, int block, int V) {
+    KArgs a = make_args(m, t, c);
+    a.V = V;
+    a.seed = p->seed;
+    a.burn_in = p->burn_in;
+    a.cycle_len = p->cycle_len;
+    a.n_perturb = p->n_perturb;
+    a.bthresh = p->birth_thresh;
+    a.sigma = p->sigma;
+    a.kappa_end = p->kappa_end;
+    a.mala_h = p->mala_h;
+    a.sampler = p->sampler;
+    a.trace = p->trace;
+    a.trace_steps = p->steps;
+    a.hist = p->hist;
+    int chunk = p->chunk > 0 ? p->chunk : p->steps;
+    for (int done = 0; done < p->steps; done += chunk) {
+        a.step0 = p->step0 + (uint64_t)done;
+        a.steps = std::min(chunk, p->steps - done);
+        a.trace_off = done;
+        hipError_t e = launch_run(a, block, s);
+        if (e != hipSuccess) return hip_fail(e, "run kernel launch");
+    }
+    return RJPATH_OK;
+}
+
+int check_run(const rjpath_medium* m, const rjpath_targets* t, const rjpath_chains* c, const rjpath_run_params* p) {
+    int r = check_common(m, t, c);
+    if (r) return r;
+    if (!p) return fail(RJPATH_EINVAL, "null run parameters");
+    if (p->steps < 0) return fail(RJPATH_EINVAL, "steps must be >= 0");
+    if (p->cycle_len < 1 || p->n_perturb < 0 || p->n_perturb > p->cycle_len)
+        return fail(RJPATH_EINVAL, "need 1 <= cycle_len and 0 <= n_perturb <= cycle_len");
+    if (p->n_perturb < p->cycle_len && (p->birth_thresh == 0u))
+        return fail(RJPATH_EINVAL, "birth_thresh must be > 0 when jump steps are scheduled");
+    if (!(p->sigma > 0) || !(p->kappa_end > 0)) return fail(RJPATH_EINVAL, "sigma and kappa_end must be > 0");
+    if (p->sampler != RJPATH_PLAIN && p->sampler != RJPATH_MALA) return fail(RJPATH_EINVAL, "bad sampler");
+    if (p->sampler == RJPATH_MALA) {
+        if (!(p->mala_h > 0)) return fail(RJPATH_EINVAL, "mala_h must be > 0");
+        if (!c->work) return fail(RJPATH_EINVAL, "the MALA sampler needs the chains' work buffer");
+    }
+    if (p->block_chains != 0 && (p->block_chains % 64 != 0 || p->block_chains < 64 || p->block_chains > 256))
+        return fail(RJPATH_EINVAL, "block_chains must be 64, 128, 192 or 256");
+    if (p->v_lds < 0 || p->v_lds > c->cap) return fail(RJPATH_EINVAL, "v_lds must lie in [0, cap]");
+    if (p->chunk < 0) return fail(RJPATH_EINVAL, "chunk must be >= 0");
+    return RJPATH_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+int rjpath_run_chains(rjpath_medium* m, const rjpath_targets* t, const rjpath_chains* c, const rjpath_run_params* p,
+                      void* stream) {
+    int r = check_run(m, t, c, p);
+    if (r) return r;
+    if (p->steps == 0) return RJPATH_OK;
+    int block, V;
+    default_launch(c->cap, c->precision, block, V);
+    auto it = m->tuned.find(TuneKey{c->cap, c->precision, p->sampler});
+    if (it != m->tuned.end()) {
+        block = it->second.first;
+        V = it->second.second;
+    }
+    if (p->block_chains) block = p->block_chains;
+    if (p->v_lds) V = p->v_lds;
+    const size_t budget = slot_budget(m, t, c);
+    if ((size_t)V * block * vtx_bytes(c->precision) > budget) {
+        if (p->v_lds) return fail(RJPATH_EINVAL, "v_lds * block_chains exceeds the LDS left after the media tables");
+        V = (int)(budget / (block * vtx_bytes(c->precision)));
+    }
+    return run_impl(m, t, c, p, (hipStream_t)stream, block, V);
+}
+
+int rjpath_autotune(rjpath_medium* m, const rjpath_targets* t, const rjpath_chains* c, const rjpath_run_params* p,
+                    int32_t steps, int32_t* best_block, int32_t* best_v, void* stream) {
+    int r = check_run(m, t, c, p);
+    if (r) return r;
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<std::pair<int, int>> cand;
+    const size_t budget = slot_budget(m, t, c);
+    for (int b : {64, 128, 256})
+        for (int v : {4, 8, 12, 16, 24, 32, 48, 64}) {
+            int vv = std::min(v, c->cap);
+            if ((size_t)vv * b * vtx_bytes(c->precision) > budget) continue;
+            if (std::find(cand.begin(), cand.end(), std::make_pair(b, vv)) == cand.end()) cand.push_back({b, vv});
+        }
+    if (steps < (int)cand.size())
+        return fail(RJPATH_EINVAL, "autotune needs steps >= " + std::to_string(cand.size()) + " (one per candidate)");
+    int trial = steps / (int)cand.size();
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0), "hipEventCreate");
+    HIPCHK(hipEventCreate(&e1), "hipEventCreate");
+    rjpath_run_params q = *p;
+    q.steps = trial;
+    q.trace = nullptr;
+    q.hist = nullptr;
+    q.chunk = 0;
+    double best = 1e300;
+    std::pair<int, int> bc = cand[0];
+    uint64_t step = p->step0;
+    for (auto& cv : cand) {
+        q.step0 = step;
+        HIPCHK(hipEventRecord(e0, s), "hipEventRecord");
+        int rr = run_impl(m, t, c, &q, s, cv.first, cv.second);
+        if (rr) return rr;
+        HIPCHK(hipEventRecord(e1, s), "hipEventRecord");
+        HIPCHK(hipEventSynchronize(e1), "hipEventSynchronize");
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+        if (ms < best) {
+            best = ms;
+            bc = cv;
+        }
+        step += trial;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    // the remainder of the requested steps with the chosen configuration
+    int rest = steps - trial * (int)cand.size();
+    if (rest > 0) {
+        q.step0 = step;
+        q.steps = rest;
+        int rr = run_impl(m, t, c, &q, s, bc.first, bc.second);
+        if (rr) return rr;
+    }
+    m->tuned[TuneKey{c->cap, c->precision, p->sampler}] = bc;
+    if (best_block) *best_block = bc.first;
+    if (best_v) *best_v = bc.second;
+    return RJPATH_OK;
+}
+
+int rjpath_grad(rjpath_medium* m, const rjpath_targets* t, const rjpath_chains* c, double* logp_out, void* dlogp_dv,
+                double* score, void* stream) {
+    int r = check_common(m, t, c);
+    if (r) return r;
+    KArgs a = make_args(m, t, c);
+    hipError_t e = launch_grad(a, logp_out, dlogp_dv, score, m->L_total, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "grad kernel launch");
+    return RJPATH_OK;
+}
+
+int rjpath_anchor(rjpath_medium* m, const rjpath_targets* t, double* anchor, void* stream) {
+    if (!anchor) return fail(RJPATH_EINVAL, "null anchor output");
+    int r = check_targets(m, t);
+    if (r) return r;
+    hipStream_t s = (hipStream_t)stream;
+    const int T = t->n_targets;
+    r = grow_ws(m, sizeof(double) * T);
+    if (r) return r;
+    KArgs a = make_args(m, t, nullptr);
+    HIPCHK(launch_anchor(a, m->d_gl, m->d_gl + 120, 120, m->d_ws, s), "anchor kernel launch");
+    HIPCHK(hipMemcpyAsync(anchor, m->d_ws, sizeof(double) * T, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+    HIPCHK(hipStreamSynchronize(s), "hipStreamSynchronize");
+    return RJPATH_OK;
+}
+
+int rjpath_intensity(rjpath_medium* m, const rjpath_targets* t, const rjpath_chains* c, int32_t groups,
+                     const double* anchor, double* I, double* se, double* ess, double* rhat, void* stream) {
+    int r = check_common(m, t, c);
+    if (r) return r;
+    if (groups < 2 || groups > 64) return fail(RJPATH_EINVAL, "groups must lie in [2, 64]");
+    hipStream_t s = (hipStream_t)stream;
+    const int T = t->n_targets;
+    std::vector<double> anc(T);
+    if (anchor) {
+        std::copy(anchor, anchor + T, anc.begin());
+    } else {
+        r = rjpath_anchor(m, t, anc.data(), stream);
+        if (r) return r;
+    }
+    size_t nred = (size_t)T * groups * RD_NW;
+    r = grow_ws(m, sizeof(double) * nred);
+    if (r) return r;
+    double* d_red = m->d_ws;
+    KArgs a = make_args(m, t, c);
+    HIPCHK(hipMemsetAsync(d_red, 0, sizeof(double) * nred, s), "hipMemsetAsync");
+    HIPCHK(launch_reduce(a, groups, d_red, s), "reduce kernel launch");
+    std::vector<double> red(nred);
+    HIPCHK(hipMemcpyAsync(red.data(), d_red, sizeof(double) * nred, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+    HIPCHK(hipStreamSynchronize(s), "hipStreamSynchronize");
+    bool nodata = false;
+    for (int ti = 0; ti < T; ++ti) {
+        const double* rt = &red[(size_t)ti * groups * RD_NW];
+        double A = 0, B = 0, chains = 0;
+        for (int g = 0; g < groups; ++g) {
+            A += rt[g * RD_NW + RD_A];
+            B += rt[g * RD_NW + RD_B];
+            chains += rt[g * RD_NW + RD_CHAINS];
+        }
+        double Ii = NAN, sei = NAN, rh = NAN;
+        if (chains > 0 && !(B > 0)) nodata = true;
+        if (B > 0) {
+            Ii = anc[ti] * A / B;
+            // delete-one-group jackknife over the non-empty groups
+            std::vector<double> jk;
+            for (int g = 0; g < groups; ++g) {
+                if (rt[g * RD_NW + RD_CHAINS] == 0) continue;
+                double Bg = B - rt[g * RD_NW + RD_B];
+                if (!(Bg > 0)) {
+                    jk.clear();
+                    break;
+                }
+                jk.push_back(anc[ti] * (A - rt[g * RD_NW + RD_A]) / Bg);
+            }
+            int G = (int)jk.size();
+            if (G >= 2) {
+                double mj = 0;
+                for (double v : jk) mj += v;
+                mj /= G;
+                double ss = 0;
+                for (double v : jk) ss += (v - mj) * (v - mj);
+                sei = std::sqrt((G - 1.0) / G * ss);
+            }
+            // potential scale reduction of the path length across groups
+            double W = 0, mb = 0, nb = 0;
+            std::vector<double> mg;
+            for (int g = 0; g < groups; ++g) {
+                double ns = rt[g * RD_NW + RD_SAMPLES];
+                if (ns < 2) continue;
+                double mu = rt[g * RD_NW + RD_L] / ns;
+                W += rt[g * RD_NW + RD_L2] / ns - mu * mu;
+                mg.push_back(mu);
+                nb += ns;
+            }
+            if (mg.size() >= 2) {
+                int k = (int)mg.size();
+                W /= k;
+                nb /= k;
+                for (double v : mg) mb += v;
+                mb /= k;
+                double Bv = 0;
+                for (double v : mg) Bv += (v - mb) * (v - mb);
+                Bv /= (k - 1);
+                if (W > 0) rh = std::sqrt(((nb - 1) / nb * W + Bv) / W);
+            }
+        }
+        if (I) I[ti] = Ii;
+        if (se) se[ti] = sei;
+        if (ess) ess[ti] = (sei > 0) ? (Ii / sei) * (Ii / sei) : NAN;
+        if (rhat) rhat[ti] = rh;
+    }
+    if (nodata) return fail(RJPATH_ENODATA, "a target has no anchor-sector visits");
+    return RJPATH_OK;
+}
+
+} // extern "C"

@@ -1,0 +1,328 @@
+// rj_device.h -- device-side building blocks of the gfx950 path sampler:
+// counter-based random numbers, precision traits, layered-medium lookups and
+// the factors of the path density (App. "Path probability distribution").
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rj_internal.h"
+
+namespace rj {
+
+// ---------------------------------------------------------------------------
+// Precision traits.  FP32 uses the hardware transcendental instructions
+// (v_log_f32, v_exp_f32, v_sqrt_f32, v_rsq_f32 and v_sin/v_cos_f32, which take
+// their argument in revolutions); FP64 uses the device libm.
+// ---------------------------------------------------------------------------
+template <class R> struct Mth;
+
+template <> struct Mth<float> {
+    static __device__ __forceinline__ float log(float x) { return __logf(x); }
+    static __device__ __forceinline__ float exp(float x) { return __expf(x); }
+    static __device__ __forceinline__ float sqrt(float x) { return __builtin_sqrtf(x); }
+    static __device__ __forceinline__ float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+    // sin / cos of 2 pi u for u in [0, 1)
+    static __device__ __forceinline__ float sin2pi(float u) { return __builtin_amdgcn_sinf(u); }
+    static __device__ __forceinline__ float cos2pi(float u) { return __builtin_amdgcn_cosf(u); }
+    static __device__ __forceinline__ float log1p(float x) { return log1pf(x); }
+    static __device__ __forceinline__ float expm1(float x) { return expm1f(x); }
+    static __device__ __forceinline__ float ninf() { return -__builtin_inff(); }
+};
+
+template <> struct Mth<double> {
+    static __device__ __forceinline__ double log(double x) { return ::log(x); }
+    static __device__ __forceinline__ double exp(double x) { return ::exp(x); }
+    static __device__ __forceinline__ double sqrt(double x) { return ::sqrt(x); }
+    static __device__ __forceinline__ double rsqrt(double x) { return 1.0 / ::sqrt(x); }
+    static __device__ __forceinline__ double sin2pi(double u) { return ::sinpi(2.0 * u); }
+    static __device__ __forceinline__ double cos2pi(double u) { return ::cospi(2.0 * u); }
+    static __device__ __forceinline__ double log1p(double x) { return ::log1p(x); }
+    static __device__ __forceinline__ double expm1(double x) { return ::expm1(x); }
+    static __device__ __forceinline__ double ninf() { return -__builtin_inf(); }
+};
+
+template <class R> struct V3 {
+    R x, y, z;
+};
+template <class R> __device__ __forceinline__ V3<R> operator+(V3<R> a, V3<R> b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+template <class R> __device__ __forceinline__ V3<R> operator-(V3<R> a, V3<R> b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+template <class R> __device__ __forceinline__ V3<R> operator*(R s, V3<R> a) { return {s * a.x, s * a.y, s * a.z}; }
+template <class R> __device__ __forceinline__ R dot(V3<R> a, V3<R> b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+
+// One path vertex as stored: position relative to the source, and w = the
+// scattering depth of the segment that leaves the vertex.
+template <class R> struct alignas(4 * sizeof(R)) Vtx {
+    R x, y, z, w;
+};
+template <class R> __device__ __forceinline__ V3<R> pos(const Vtx<R>& v) { return {v.x, v.y, v.z}; }
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): two 32x32->64 products per round via
+// v_mad_u64_u32, Weyl key schedule.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+        uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
+        uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = (uint32_t)p1;
+        c[2] = n2;
+        c[3] = (uint32_t)p0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+// Uniform in (0,1) from the top 23 bits: exact in FP32 and FP64 alike.
+template <class R> __device__ __forceinline__ R unif(uint32_t x) { return ((R)(x >> 9) + (R)0.5) * (R)0x1p-23; }
+// floor(x * m / 2^32)
+__device__ __forceinline__ int pick(uint32_t x, uint32_t m) { return (int)__umulhi(x, m); }
+
+// ---------------------------------------------------------------------------
+// Layer constants (values, so a homogeneous medium keeps them in registers).
+// ---------------------------------------------------------------------------
+template <class R> struct LayV {
+    R a, b, c, logb, g, hgn, hg1, keq, fsl, sln, sla;
+};
+
+template <class R> __device__ __forceinline__ LayV<R> lay_load(const R* p) {
+    return LayV<R>{p[LY_A], p[LY_B], p[LY_C], p[LY_LOGB], p[LY_G], p[LY_HGN],
+                   p[LY_HG1], p[LY_KEQ], p[LY_FSL], p[LY_SLN], p[LY_SLA]};
+}
+
+// ---------------------------------------------------------------------------
+// Per-chain view of its target: sensor, emission, detection and medium.
+// ---------------------------------------------------------------------------
+template <class R> struct Tgt {
+    V3<R> eta;    // sensor centre relative to the source
+    R rad;        // sensor radius
+    int ek;       // emission kind
+    V3<R> ed;     // emission axis
+    R kappa;      // vMF concentration
+    R elog;       // log of the emission normalisation
+    R ecos;       // cone: cos(half-angle)
+    int dk;       // detection kind
+    V3<R> dd;     // detection axis
+    int n0;       // anchor sector
+    // medium
+    int mcnt, uniform;
+    double ax, ay, az, e0, inv_h, usrc;
+    LayV<R> l0;          // layer 0 (the only one of a homogeneous medium)
+    const R* lay;        // layer table of this medium (LY_NW per layer), LDS or HBM
+    const double* edge;  // edges of this medium (mcnt + 1)
+    const double2* pre;  // prefix integrals (c, b) at the edges
+};
+
+template <class R> __device__ __forceinline__ LayV<R> lay_at(const Tgt<R>& T, int l) {
+    if (T.mcnt == 1) return T.l0;
+    return lay_load(T.lay + l * LY_NW);
+}
+
+template <class R> __device__ __forceinline__ double axis_u(const Tgt<R>& T, V3<R> p) {
+    return T.usrc + T.ax * (double)p.x + T.ay * (double)p.y + T.az * (double)p.z;
+}
+
+// Layer l with edge_l <= u < edge_{l+1}, outer layers unbounded.
+template <class R> __device__ __forceinline__ int layer_u(const Tgt<R>& T, double u) {
+    int cnt = T.mcnt;
+    if (cnt == 1) return 0;
+    int l;
+    if (T.uniform) {
+        double q = floor((u - T.e0) * T.inv_h);
+        l = q < 0.0 ? 0 : (q >= (double)(cnt - 1) ? cnt - 1 : (int)q);
+        // settle rounding against the stored edges
+        if (l > 0 && u < T.edge[l]) --l;
+        else if (l + 1 < cnt && u >= T.edge[l + 1]) ++l;
+    } else {
+        int lo = 0, hi = cnt - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (u >= T.edge[mid]) lo = mid; else hi = mid - 1;
+        }
+        l = lo;
+    }
+    return l;
+}
+
+template <class R> __device__ __forceinline__ int layer_at(const Tgt<R>& T, V3<R> p) {
+    if (T.mcnt == 1) return 0;
+    return layer_u(T, axis_u(T, p));
+}
+
+template <class R> __device__ __forceinline__ LayV<R> lay_of(const Tgt<R>& T, V3<R> p) {
+    if (T.mcnt == 1) return T.l0;
+    return lay_load(T.lay + layer_u(T, axis_u(T, p)) * LY_NW);
+}
+
+// Optical depths of the segment P -> Q of length len: total c = a + b and
+// scattering b; exact piecewise integral along the layer axis (the length
+// factor of the depth definition restored).  The crossing case is done in
+// FP64 so that short crossings of a layer boundary keep their precision.
+template <class R>
+__device__ __forceinline__ void seg_depth(const Tgt<R>& T, V3<R> P, V3<R> Q, R len, R& tc, R& tb) {
+    if (T.mcnt == 1) {
+        tc = T.l0.c * len;
+        tb = T.l0.b * len;
+        return;
+    }
+    double uP = axis_u(T, P), uQ = axis_u(T, Q);
+    int lP = layer_u(T, uP), lQ = layer_u(T, uQ);
+    if (lP == lQ) {
+        const R* ly = T.lay + lP * LY_NW;
+        tc = ly[LY_C] * len;
+        tb = ly[LY_B] * len;
+        return;
+    }
+    double lo = uP, hi = uQ;
+    int llo = lP, lhi = lQ;
+    if (uP > uQ) {
+        lo = uQ; hi = uP; llo = lQ; lhi = lP;
+    }
+    const R* a = T.lay + llo * LY_NW;
+    const R* b = T.lay + lhi * LY_NW;
+    double eh = T.edge[llo + 1], el = T.edge[lhi];
+    double2 ph = T.pre[llo + 1], pl = T.pre[lhi];
+    double Ic = (double)a[LY_C] * (eh - lo) + (pl.x - ph.x) + (double)b[LY_C] * (hi - el);
+    double Ib = (double)a[LY_B] * (eh - lo) + (pl.y - ph.y) + (double)b[LY_B] * (hi - el);
+    double inv = 1.0 / (hi - lo);
+    tc = (R)(Ic * inv) * len;
+    tb = (R)(Ib * inv) * len;
+}
+
+// log of the per-steradian scattering function at a vertex with incoming and
+// outgoing unit directions ua, ub; 1 - mu = |ua - ub|^2 / 2 keeps the forward
+// peak accurate in FP32.
+template <class R> __device__ __forceinline__ R turn_term(const LayV<R>& ly, V3<R> ua, V3<R> ub) {
+    V3<R> d = ua - ub;
+    R q = dot(d, d); // 2 (1 - mu)
+    R hg = ly.hgn - (R)1.5 * Mth<R>::log(ly.hg1 + ly.g * q);
+    if (ly.fsl == (R)0) return hg;
+    R sl = ly.sln + ly.sla * Mth<R>::log((R)1 - (R)0.25 * q);
+    R m = sl > hg ? sl : hg;
+    return m + Mth<R>::log(ly.fsl * Mth<R>::exp(sl - m) + ((R)1 - ly.fsl) * Mth<R>::exp(hg - m));
+}
+
+// log of the emission density at the first direction u0 (eq. emission_dist
+// and the isotropic / cone forms).
+template <class R> __device__ __forceinline__ R emit_term(const Tgt<R>& T, V3<R> u0) {
+    if (T.ek == RJPATH_EMIT_ISO) return T.elog;
+    if (T.ek == RJPATH_EMIT_VMF) {
+        V3<R> d = u0 - T.ed;
+        return T.elog - (R)0.5 * T.kappa * dot(d, d); // kappa (u.e - 1) + log norm
+    }
+    return dot(u0, T.ed) >= T.ecos ? T.elog : Mth<R>::ninf();
+}
+
+// log of the final factor without its segment terms: log max(0, -u . nu) +
+// log rho(nu), with nu the outward normal at the end point fe.
+template <class R> __device__ __forceinline__ R end_term(const Tgt<R>& T, V3<R> ul, V3<R> fe) {
+    V3<R> d = fe - T.eta;
+    V3<R> nu = Mth<R>::rsqrt(dot(d, d)) * d;
+    R c = -dot(ul, nu);
+    if (!(c > (R)0)) return Mth<R>::ninf();
+    R t = Mth<R>::log(c);
+    if (T.dk == RJPATH_DET_PAPER) {
+        R cr = dot(nu, T.dd);
+        R z = (R)2 * cr + (R)0.7;
+        // log cosh z = |z| + log1p(e^{-2|z|}) - log 2
+        R az = z < (R)0 ? -z : z;
+        t += (R)3 * cr - (R)1 - (az + Mth<R>::log1p(Mth<R>::exp((R)-2 * az)) - (R)0.69314718055994530942);
+    }
+    return t;
+}
+
+// A straight segment: unit direction, length, log length and depths.
+template <class R> struct Seg {
+    V3<R> u;
+    R len, loglen, tc, tb;
+};
+
+template <class R> __device__ __forceinline__ Seg<R> make_seg(const Tgt<R>& T, V3<R> P, V3<R> Q) {
+    Seg<R> s;
+    V3<R> r = Q - P;
+    R l2 = dot(r, r);
+    R il = Mth<R>::rsqrt(l2);
+    s.u = il * r;
+    s.len = l2 * il;
+    s.loglen = (R)0.5 * Mth<R>::log(l2);
+    seg_depth(T, P, Q, s.len, s.tc, s.tb);
+    return s;
+}
+
+// -tau_a - tau_b - 2 log |r| of a segment (each segment carries one
+// attenuation and one inverse-square factor, p_v and p_f alike).
+template <class R> __device__ __forceinline__ R seg_term(const Seg<R>& s) { return -s.tc - (R)2 * s.loglen; }
+
+template <class R> __device__ __forceinline__ V3<R> unit_dir(V3<R> P, V3<R> Q) {
+    V3<R> r = Q - P;
+    return Mth<R>::rsqrt(dot(r, r)) * r;
+}
+
+// Orthonormal completion of a unit vector (Duff et al., JCGT 2017).
+template <class R> __device__ __forceinline__ void onb(V3<R> n, V3<R>& e2, V3<R>& e3) {
+    R sgn = copysign((R)1, n.z);
+    R a = (R)-1 / (sgn + n.z);
+    R b = n.x * n.y * a;
+    e2 = {(R)1 + sgn * n.x * n.x * a, sgn * b, -sgn * n.x};
+    e3 = {b, sgn + n.y * n.y * a, -n.y};
+}
+
+// Where the media tables are read from during a launch (LDS copy or HBM).
+template <class R> struct MedTab {
+    const R* lay;
+    const double* edge;
+    const double* pre;
+};
+
+// Loads the view of target t.  `tab` gives the layer tables (the FP64 table
+// for the FP64 quadratures regardless of the chains' precision).
+template <class R>
+__device__ __forceinline__ void load_target(const KArgs& a, int t, Tgt<R>& T, const MedTab<R>& tab) {
+    const double* s = a.sensor + 3 * t;
+    const double* o = a.src + 3 * t;
+    T.eta = {(R)(s[0] - o[0]), (R)(s[1] - o[1]), (R)(s[2] - o[2])};
+    T.rad = (R)a.radius[t];
+    T.ek = a.ek[t];
+    T.ed = {(R)a.edir[3 * t], (R)a.edir[3 * t + 1], (R)a.edir[3 * t + 2]};
+    double ep = a.eparam[t];
+    const double PI = 3.14159265358979323846;
+    T.kappa = (R)ep;
+    T.ecos = (R)0;
+    if (T.ek == RJPATH_EMIT_ISO) {
+        T.elog = (R)(-log(4.0 * PI));
+    } else if (T.ek == RJPATH_EMIT_VMF) {
+        // kappa e^{kappa u.e} / (4 pi sinh kappa) = e^{kappa (u.e - 1)} kappa / (2 pi (1 - e^{-2 kappa}))
+        T.elog = (R)(log(ep) - log(2.0 * PI) - log1p(-exp(-2.0 * ep)));
+    } else {
+        double ca = cos(ep);
+        T.ecos = (R)ca;
+        T.elog = (R)(-log(2.0 * PI * (1.0 - ca)));
+    }
+    T.dk = a.dk[t];
+    T.dd = {(R)a.ddir[3 * t], (R)a.ddir[3 * t + 1], (R)a.ddir[3 * t + 2]};
+    T.n0 = a.n0[t];
+    const MedInfo mi = a.minfo[a.medium[t]];
+    T.mcnt = mi.cnt;
+    T.uniform = mi.uniform;
+    T.ax = mi.ax;
+    T.ay = mi.ay;
+    T.az = mi.az;
+    T.e0 = mi.e0;
+    T.inv_h = mi.inv_h;
+    T.usrc = mi.ax * o[0] + mi.ay * o[1] + mi.az * o[2];
+    T.lay = tab.lay + (size_t)mi.off * LY_NW;
+    T.l0 = lay_load(T.lay);
+    int eo = mi.off + a.medium[t];
+    T.edge = tab.edge + eo;
+    T.pre = (const double2*)tab.pre + eo;
+}
+
+template <class R> __device__ __forceinline__ MedTab<R> hbm_tab(const KArgs& a) {
+    return MedTab<R>{(const R*)a.lay, a.edge, a.pre};
+}
+
+} // namespace rj

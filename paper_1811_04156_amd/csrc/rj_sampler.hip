@@ -1,0 +1,759 @@
+// rj_sampler.hip -- the fused reversible-jump step kernel for gfx950.
+//
+// One chain per lane.  A block owns a tile of chains for every step of the
+// launch.  The first V vertices of each chain live in LDS in a vertex-major,
+// lane-minor layout ([slot][lane]: per-lane random slots stay conflict-free),
+// the rest stay in the caller's HBM array (same [v][C] layout, read and
+// written coalesced at launch start and end).  When every lane of a wave fits
+// its LDS slots (a wave vote per step) the step runs a branch-free LDS-only
+// instantiation.  Layered media are staged in LDS once per block; a
+// homogeneous medium lives in registers.
+//
+// Every step of a launch is the same move class for all lanes (the move
+// schedule depends only on the global step index), so waves diverge only
+// inside a class: interior and end-point perturbations share one
+// local-density evaluator, births and deaths share one jump evaluator.
+//
+// Method references: path density (App. "Path probability distribution"),
+// jump proposal and bi-spherical map (App. "Jump proposal", "Dimension
+// matching transformation"), acceptance (eq. acceptFact read in Green's
+// form), end-point move on the sensor and proposal mix (Sec. "Path proposal
+// distribution"); the Langevin move follows the Discussion's suggestion of
+// gradient-informed moves.
+#include <hip/hip_runtime.h>
+
+#include "rj_device.h"
+#include "rj_kernels.h"
+
+namespace rj {
+
+enum { MV_INTERIOR = 0, MV_END = 1, MV_BIRTH = 2, MV_DEATH = 3, MV_MALA = 4, MV_NULL = 5 };
+
+// Lane-private path storage: slots below V in LDS, the rest in HBM.  LO: the
+// whole path is known to be in LDS.
+template <class R, bool LO> struct PathRef {
+    Vtx<R>* lds; // this lane's slot 0, stride bs
+    Vtx<R>* glb; // this chain's vertex 0, stride C
+    int bs, V;
+    size_t C;
+    __device__ __forceinline__ Vtx<R> ld(int v) const {
+        if (LO) return lds[v * bs];
+        return v < V ? lds[v * bs] : glb[(size_t)v * C];
+    }
+    __device__ __forceinline__ void st(int v, const Vtx<R>& x) const {
+        if (LO || v < V) lds[v * bs] = x;
+        else glb[(size_t)v * C] = x;
+    }
+    __device__ __forceinline__ V3<R> p(int v) const { return pos(ld(v)); }
+    __device__ __forceinline__ R w(int v) const {
+        if (LO) return lds[v * bs].w;
+        return v < V ? lds[v * bs].w : glb[(size_t)v * C].w;
+    }
+    __device__ __forceinline__ void stw(int v, R x) const {
+        if (LO || v < V) lds[v * bs].w = x;
+        else glb[(size_t)v * C].w = x;
+    }
+};
+
+template <class R> struct GlobalPath {
+    Vtx<R>* glb;
+    size_t C;
+    __device__ __forceinline__ Vtx<R> ld(int v) const { return glb[(size_t)v * C]; }
+    __device__ __forceinline__ V3<R> p(int v) const { return pos(ld(v)); }
+    __device__ __forceinline__ void stw(int, R) const {}
+};
+
+// Fixed-point images (x * 2^bits, truncated) of the cached segment scattering
+// depths (2^40) and lengths (2^32).  Integer sums are associative, so a sum
+// kept by incremental updates equals a fresh re-summation bit for bit and a
+// chain's trajectory does not depend on where launches start and end.  The
+// FP32 form works on the bit pattern (no FP64 conversion).
+__device__ __forceinline__ long long fxb(float x, int bits) {
+    uint32_t u = __float_as_uint(x);
+    int e = (int)((u >> 23) & 0xffu);
+    if (e == 0 || (u >> 31)) return 0; // zero, subnormal (below 2^-126) or negative
+    uint64_t m = (uint64_t)((u & 0x7fffffu) | 0x800000u);
+    int s = e - 150 + bits; // value = m * 2^(e - 150)
+    s = s > 39 ? 39 : s;
+    return (long long)(s >= 0 ? (m << s) : (s > -64 ? (m >> -s) : 0));
+}
+__device__ __forceinline__ long long fxb(double x, int bits) { return (long long)(x * ldexp(1.0, bits)); }
+template <class R> __device__ __forceinline__ long long fxs(R x) { return fxb(x, 40); }
+template <class R> __device__ __forceinline__ long long fxl(R x) { return fxb(x, 32); }
+
+// Full log p of the path (FP64 sum of the factors), refreshing the cached
+// segment scattering depths; also returns S = sum tau_b and the length L
+// (fixed point).
+template <class R, class P>
+__device__ __forceinline__ double full_logp(const Tgt<R>& T, const P& ps, int n, long long& S, long long& L) {
+    V3<R> f0 = ps.p(0), f1 = ps.p(1);
+    Seg<R> s = make_seg(T, f0, f1);
+    bool zero = !(s.len > (R)0);
+    double lp = (double)emit_term(T, s.u) + (double)seg_term(s);
+    S = fxs(s.tb);
+    L = fxl(s.len);
+    ps.stw(0, s.tb);
+    V3<R> fc = f1;
+    for (int k = 1; k <= n - 2; ++k) {
+        V3<R> fn = ps.p(k + 1);
+        Seg<R> s2 = make_seg(T, fc, fn);
+        zero |= !(s2.len > (R)0);
+        const LayV<R> ly = lay_of(T, fc);
+        lp += (double)(ly.logb + turn_term(ly, s.u, s2.u)) + (double)seg_term(s2);
+        S += fxs(s2.tb);
+        L += fxl(s2.len);
+        ps.stw(k, s2.tb);
+        s = s2;
+        fc = fn;
+    }
+    lp += (double)end_term(T, s.u, fc);
+    if (zero) lp = -__builtin_inf();
+    return lp;
+}
+
+// log((1 - e^{-2 beta}) / beta) = log(2 sinh(beta) / beta) - beta
+template <class R> __device__ __forceinline__ R ls2(R beta) {
+    R ab = beta < (R)0 ? -beta : beta;
+    if (ab < (R)1e-6) return (R)0.69314718055994530942 - beta;
+    return Mth<R>::log(-Mth<R>::expm1((R)-2 * beta) / beta);
+}
+
+template <class R>
+__device__ __forceinline__ void box_muller3(uint32_t a, uint32_t b, uint32_t c, uint32_t d, V3<R>& xi) {
+    R u0 = unif<R>(a), u1 = unif<R>(b), u2 = unif<R>(c), u3 = unif<R>(d);
+    R rho1 = Mth<R>::sqrt((R)-2 * Mth<R>::log(u0));
+    R rho2 = Mth<R>::sqrt((R)-2 * Mth<R>::log(u2));
+    xi = {rho1 * Mth<R>::cos2pi(u1), rho1 * Mth<R>::sin2pi(u1), rho2 * Mth<R>::cos2pi(u3)};
+}
+
+// ---------------------------------------------------------------------------
+// Score of the path: log p and d log p / d vertex, streamed along the path
+// with a three-vertex register window.  emit(k, g) receives the finished
+// gradient of vertex k (k = 0 .. n-1, in increasing order).
+// ---------------------------------------------------------------------------
+template <class R>
+__device__ __forceinline__ void seg_depth_grad(const Tgt<R>& T, V3<R> P, V3<R> Q, const Seg<R>& s, V3<R>& dP,
+                                               V3<R>& dQ) {
+    R F = s.tc / s.len; // mean total coefficient along the segment
+    dP = (-F) * s.u;
+    dQ = F * s.u;
+    if (T.mcnt > 1) {
+        double uP = axis_u(T, P), uQ = axis_u(T, Q);
+        int lP = layer_u(T, uP), lQ = layer_u(T, uQ);
+        if (lP != lQ) {
+            double cP = (double)T.lay[lP * LY_NW + LY_C], cQ = (double)T.lay[lQ * LY_NW + LY_C];
+            double inv = 1.0 / (uQ - uP);
+            R gP = (R)((double)s.len * ((double)F - cP) * inv);
+            R gQ = (R)((double)s.len * (cQ - (double)F) * inv);
+            V3<R> ax = {(R)T.ax, (R)T.ay, (R)T.az};
+            dP = dP + gP * ax;
+            dQ = dQ + gQ * ax;
+        }
+    }
+}
+
+// d log sigma / d mu at a turn, q = |ua - ub|^2
+template <class R> __device__ __forceinline__ R dturn_dmu(const LayV<R>& ly, R q) {
+    R den = ly.hg1 + ly.g * q;
+    R dhg = (R)3 * ly.g / den;
+    if (ly.fsl == (R)0) return dhg;
+    R hg = ly.hgn - (R)1.5 * Mth<R>::log(den);
+    R v = (R)1 - (R)0.25 * q; // (1 + mu) / 2
+    R sl = ly.sln + ly.sla * Mth<R>::log(v);
+    R dsl = ly.sla / ((R)2 * v);
+    R m = sl > hg ? sl : hg;
+    R es = ly.fsl * Mth<R>::exp(sl - m), eh = ((R)1 - ly.fsl) * Mth<R>::exp(hg - m);
+    return (es * dsl + eh * dhg) / (es + eh);
+}
+
+template <class R> __device__ __forceinline__ V3<R> dunit(V3<R> u, R len, V3<R> c) {
+    // d (u . c) / d r for u = r / |r|
+    R il = (R)1 / len;
+    return il * (c - dot(u, c) * u);
+}
+
+template <class R, class P, class Emit>
+__device__ __forceinline__ double score_stream(const Tgt<R>& T, const P& ps, int n, Emit emit) {
+    V3<R> z = {(R)0, (R)0, (R)0};
+    V3<R> gA = z, gB = z, gC = z; // vertices k-2, k-1, k
+    V3<R> fprev = ps.p(0), fcur;
+    Seg<R> sprev;
+    double lp = 0.0;
+    bool zero = false;
+    for (int k = 1; k < n; ++k) {
+        fcur = ps.p(k);
+        Seg<R> s = make_seg(T, fprev, fcur);
+        zero |= !(s.len > (R)0);
+        lp += (double)seg_term(s);
+        V3<R> dP, dQ;
+        seg_depth_grad(T, fprev, fcur, s, dP, dQ);
+        R il2 = (R)2 / s.len;
+        gB = gB - dP + il2 * s.u;
+        gC = gC - dQ - il2 * s.u;
+        if (k == 1) {
+            lp += (double)emit_term(T, s.u);
+            if (T.ek == RJPATH_EMIT_VMF) {
+                V3<R> d = T.kappa * dunit(s.u, s.len, T.ed);
+                gC = gC + d;
+                gB = gB - d;
+            }
+        } else {
+            // turn (and scattering density) at vertex k-1 between sprev and s
+            const LayV<R> ly = lay_of(T, fprev);
+            V3<R> dd = sprev.u - s.u;
+            lp += (double)(ly.logb + turn_term(ly, sprev.u, s.u));
+            R h = dturn_dmu(ly, dot(dd, dd));
+            V3<R> da = dunit(sprev.u, sprev.len, s.u);
+            V3<R> db = dunit(s.u, s.len, sprev.u);
+            gA = gA - h * da;
+            gB = gB + h * da - h * db;
+            gC = gC + h * db;
+            emit(k - 2, gA);
+        }
+        gA = gB;
+        gB = gC;
+        gC = z;
+        sprev = s;
+        fprev = fcur;
+    }
+    // end term on segment n-2 and the end point (gA = vertex n-2, gB = vertex n-1)
+    lp += (double)end_term(T, sprev.u, fprev);
+    V3<R> d = fprev - T.eta;
+    R dn2 = dot(d, d);
+    R idn = Mth<R>::rsqrt(dn2);
+    V3<R> nu = idn * d;
+    R c = -dot(sprev.u, nu);
+    R ic = (R)1 / c;
+    V3<R> dcr = (R)-1 * dunit(sprev.u, sprev.len, nu);
+    V3<R> dcd = (R)-1 * dunit(nu, dn2 * idn, sprev.u);
+    gA = gA - ic * dcr;
+    gB = gB + ic * dcr + ic * dcd;
+    if (T.dk == RJPATH_DET_PAPER) {
+        R cr = dot(nu, T.dd);
+        R th = tanh((R)2 * cr + (R)0.7);
+        gB = gB + ((R)3 - (R)2 * th) * dunit(nu, dn2 * idn, T.dd);
+    }
+    if (n >= 3) emit(n - 2, gA);
+    emit(n - 1, gB);
+    if (zero) lp = -__builtin_inf();
+    return lp;
+}
+
+// ---------------------------------------------------------------------------
+// Per-lane sampler state and statistics.
+// ---------------------------------------------------------------------------
+template <class R> struct Lane {
+    int n;
+    long long S, L; // fixed-point sum of cached depths and path length
+    double lp;      // cached log p (refreshed at launch start)
+    double invw;    // 1 / w(n)
+    // statistics of this launch
+    double a1, a2, sl2;
+    long long sl;
+    uint32_t cnt, sn, ncap, pp, pb, pd, ap, ab, ad, mp, ma;
+};
+
+struct StepCtx {
+    uint32_t chain, k0, k1;
+    int cap;
+    uint32_t bthresh;
+    float log_pb, log_pd;
+    double sigma, kappa, e2k, mala_h;
+    int sampler;
+    const double* logw;
+};
+
+// One step of one lane; returns the move kind, writes log A / accepted / index.
+template <class R, bool LO, bool MALA>
+__device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>& ps, const GlobalPath<R>& work,
+                                          Lane<R>& ln, const StepCtx& sc, uint64_t step, bool perturb, int& move,
+                                          int& idx, int& accepted, R& logA, R& logu) {
+    uint32_t r[8];
+    {
+        uint32_t q0[4] = {sc.chain, (uint32_t)step, (uint32_t)(step >> 32), 0u};
+        uint32_t q1[4] = {sc.chain, (uint32_t)step, (uint32_t)(step >> 32), 1u};
+        philox4x32_10(q0, sc.k0, sc.k1);
+        philox4x32_10(q1, sc.k0, sc.k1);
+        r[0] = q0[0]; r[1] = q0[1]; r[2] = q0[2]; r[3] = q0[3];
+        r[4] = q1[0]; r[5] = q1[1]; r[6] = q1[2]; r[7] = q1[3];
+    }
+    const int n = ln.n;
+    logu = Mth<R>::log(unif<R>(r[1]));
+    move = MV_NULL;
+    idx = -1;
+    accepted = 0;
+    logA = Mth<R>::ninf();
+    if (perturb) {
+        const int j = 1 + pick(r[0], (uint32_t)(n - 1));
+        idx = j;
+        const bool is_end = (j == n - 1);
+        if (MALA && !is_end) {
+            // ---------- joint Langevin move of all interior vertices ----------
+            move = MV_MALA;
+            const R h = (R)sc.mala_h, hh = (R)0.5 * h, sh = Mth<R>::sqrt(h);
+            double half_xi2 = 0.0;
+            double lpx = score_stream(T, ps, n, [&](int k, V3<R> g) {
+                Vtx<R> x = ps.ld(k);
+                V3<R> y = pos(x);
+                if (k >= 1 && k <= n - 2) {
+                    uint32_t q[4] = {sc.chain, (uint32_t)step, (uint32_t)(step >> 32), 2u + (uint32_t)k};
+                    philox4x32_10(q, sc.k0, sc.k1);
+                    V3<R> xi;
+                    box_muller3<R>(q[0], q[1], q[2], q[3], xi);
+                    half_xi2 += 0.5 * (double)dot(xi, xi);
+                    y = y + hh * g + sh * xi;
+                }
+                work.glb[(size_t)k * work.C] = Vtx<R>{y.x, y.y, y.z, (R)0};
+            });
+            double rev = 0.0;
+            double lpy = score_stream(T, work, n, [&](int k, V3<R> g) {
+                if (k >= 1 && k <= n - 2) {
+                    V3<R> d = ps.p(k) - work.p(k) - hh * g;
+                    rev += (double)dot(d, d) / (2.0 * (double)h);
+                }
+            });
+            double la = lpy - lpx - rev + half_xi2;
+            logA = isfinite(lpy) ? (R)la : Mth<R>::ninf();
+            if (logu < logA) {
+                accepted = 1;
+                for (int k = 1; k <= n - 2; ++k) ps.st(k, work.ld(k));
+                ln.lp = full_logp(T, ps, n, ln.S, ln.L);
+            }
+            return;
+        }
+        // ---------- single-vertex perturbation (interior Gaussian or end-point vMF) ----------
+        const V3<R> fo = ps.p(j);
+        V3<R> fn;
+        if (!is_end) {
+            move = MV_INTERIOR;
+            V3<R> xi;
+            box_muller3<R>(r[4], r[5], r[6], r[7], xi);
+            fn = fo + (R)sc.sigma * xi;
+        } else {
+            move = MV_END;
+            V3<R> d = fo - T.eta;
+            V3<R> nu = Mth<R>::rsqrt(dot(d, d)) * d, e2, e3;
+            onb(nu, e2, e3);
+            R u = unif<R>(r[4]);
+            R omw = -Mth<R>::log(u + ((R)1 - u) * (R)sc.e2k) / (R)sc.kappa; // 1 - cos
+            R w = (R)1 - omw;
+            R sw = Mth<R>::sqrt(omw * ((R)2 - omw));
+            R ph = unif<R>(r[5]);
+            V3<R> nn = w * nu + sw * (Mth<R>::cos2pi(ph) * e2 + Mth<R>::sin2pi(ph) * e3);
+            fn = T.eta + T.rad * nn;
+        }
+        const bool hm2 = j >= 2, hp1 = j <= n - 2, hp2 = j <= n - 3;
+        const V3<R> fm1 = ps.p(j - 1);
+        const Seg<R> Ao = make_seg(T, fm1, fo), An = make_seg(T, fm1, fn);
+        R d = seg_term(An) - seg_term(Ao);
+        Seg<R> Bo, Bn;
+        V3<R> fp1;
+        if (hp1) {
+            fp1 = ps.p(j + 1);
+            Bo = make_seg(T, fo, fp1);
+            Bn = make_seg(T, fn, fp1);
+            d += seg_term(Bn) - seg_term(Bo);
+            const LayV<R> lo = lay_of(T, fo), lnw = lay_of(T, fn);
+            d += (lnw.logb + turn_term(lnw, An.u, Bn.u)) - (lo.logb + turn_term(lo, Ao.u, Bo.u));
+            if (hp2) {
+                V3<R> up = unit_dir(fp1, ps.p(j + 2));
+                const LayV<R> l1 = lay_of(T, fp1);
+                d += turn_term(l1, Bn.u, up) - turn_term(l1, Bo.u, up);
+            } else {
+                d += end_term(T, Bn.u, fp1) - end_term(T, Bo.u, fp1);
+            }
+        } else {
+            d += end_term(T, An.u, fn) - end_term(T, Ao.u, fo);
+        }
+        if (hm2) {
+            V3<R> um = unit_dir(ps.p(j - 2), fm1);
+            const LayV<R> l1 = lay_of(T, fm1);
+            d += turn_term(l1, um, An.u) - turn_term(l1, um, Ao.u);
+        } else {
+            d += emit_term(T, An.u) - emit_term(T, Ao.u);
+        }
+        logA = d;
+        if (logu < logA) {
+            accepted = 1;
+            ps.st(j, Vtx<R>{fn.x, fn.y, fn.z, hp1 ? Bn.tb : (R)0});
+            ps.stw(j - 1, An.tb);
+            ln.lp += (double)d;
+            ln.S += fxs(An.tb) - fxs(Ao.tb);
+            ln.L += fxl(An.len) - fxl(Ao.len);
+            if (hp1) {
+                ln.S += fxs(Bn.tb) - fxs(Bo.tb);
+                ln.L += fxl(Bn.len) - fxl(Bo.len);
+            }
+        }
+        return;
+    }
+    // ---------- birth / death through the bi-spherical map ----------
+    const bool birth = r[2] < sc.bthresh;
+    move = birth ? MV_BIRTH : MV_DEATH;
+    const bool valid = birth ? (n < sc.cap && ln.S > 0) : (n > 2);
+    int iA = 0, jv = 1;
+    if (valid) {
+        if (birth) {
+            // segment k with probability tau_b(k) / S: scan of the cached depths
+            const long long tgt = (long long)((double)unif<double>(r[0]) * (double)ln.S);
+            long long cum = 0;
+            int k = n - 2;
+            for (int v = 0; v < n - 1; ++v) {
+                cum += fxs(ps.w(v));
+                if (cum > tgt) {
+                    k = v;
+                    break;
+                }
+            }
+            iA = k;
+        } else {
+            jv = 1 + pick(r[0], (uint32_t)(n - 2));
+            iA = jv - 1;
+        }
+        idx = birth ? iA : jv;
+    }
+    const int iB = birth ? iA + 1 : iA + 2;
+    const V3<R> A = ps.p(iA), B = ps.p(iB < n ? iB : n - 1);
+    const Seg<R> AB = make_seg(T, A, B);
+    const V3<R> mid = (R)0.5 * (A + B);
+    const LayV<R> lm = lay_of(T, mid);
+    const R gam = (R)0.5 * AB.len;
+    const R beta = lm.keq + (R)0.5 * (gam * lm.b - (R)1); // centering rule at the midpoint
+    V3<R> fv;
+    if (birth) {
+        R u4 = unif<R>(r[4]);
+        R ab = beta < (R)0 ? -beta : beta;
+        // w = 1 + cos s by the inverse CDF of q(s)
+        R w = ab < (R)1e-6 ? (R)2 * ((R)1 - u4) : -Mth<R>::log1p(((R)1 - u4) * Mth<R>::expm1((R)-2 * beta)) / beta;
+        // t from the logistic q(t): e^t = a/(1-a); sinh t and cosh t - cos s in closed form
+        R a5 = unif<R>(r[5]), b5 = (R)1 - a5, ab2 = (R)2 * a5 * b5;
+        R ss = Mth<R>::sqrt(fmax(w * ((R)2 - w), (R)0));
+        R ph = unif<R>(r[6]);
+        V3<R> e2, e3;
+        onb(AB.u, e2, e3);
+        R sc_ = gam / ((R)1 - ab2 * w);
+        V3<R> tr = Mth<R>::cos2pi(ph) * e2 + Mth<R>::sin2pi(ph) * e3;
+        fv = mid + sc_ * ((a5 - b5) * AB.u + (ab2 * ss) * tr);
+    } else {
+        fv = ps.p(jv);
+    }
+    const bool hprev = iA >= 1, hnext = iB + 1 <= n - 1;
+    const Seg<R> sA = make_seg(T, A, fv), sB = make_seg(T, fv, B);
+    R tx = (R)0, ty = (R)0;
+    if (hprev) {
+        V3<R> up = unit_dir(ps.p(iA - 1), A);
+        const LayV<R> la = lay_of(T, A);
+        tx += turn_term(la, up, AB.u);
+        ty += turn_term(la, up, sA.u);
+    } else {
+        tx += emit_term(T, AB.u);
+        ty += emit_term(T, sA.u);
+    }
+    if (hnext) {
+        V3<R> un = unit_dir(B, ps.p(iB + 1));
+        const LayV<R> lb = lay_of(T, B);
+        tx += turn_term(lb, AB.u, un);
+        ty += turn_term(lb, sB.u, un);
+    } else {
+        tx += end_term(T, AB.u, B);
+        ty += end_term(T, sB.u, B);
+    }
+    const LayV<R> lv = lay_of(T, fv);
+    V3<R> dq = sA.u - sB.u;
+    R q = dot(dq, dq);
+    ty += lv.logb + turn_term(lv, sA.u, sB.u);
+    // segment factors of y over x times |J| / q(s) q(t) q(phi): the inverse-square
+    // factors of the two new segments cancel against J; 1 + cos s = q / 2
+    const R LOG2PI = (R)1.83787706640934548356;
+    R jac = -sA.tc - sB.tc + AB.tc + (R)2 * Mth<R>::log(sA.len + sB.len) - AB.loglen + ls2(beta) +
+            (R)0.5 * beta * q + LOG2PI;
+    const int nx = birth ? n : n - 1;
+    const long long Sx = birth ? ln.S : ln.S - fxs(ps.w(iA)) - fxs(ps.w(jv)) + fxs(AB.tb);
+    R lpup = (R)sc.log_pb + Mth<R>::log(AB.tb) - Mth<R>::log((R)((double)Sx * 0x1p-40));
+    R lpdn = (R)sc.log_pd - Mth<R>::log((R)(nx - 1));
+    R dlw = (sc.logw && valid) ? (R)(sc.logw[nx + 1] - sc.logw[nx]) : (R)0;
+    R logAb = (ty - tx) + jac + dlw + lpdn - lpup;
+    logA = valid ? (birth ? logAb : -logAb) : Mth<R>::ninf();
+    if (logu < logA) {
+        accepted = 1;
+        R dlp = (ty - tx) + seg_term(sA) + seg_term(sB) - seg_term(AB);
+        if (birth) {
+            for (int v = n - 1; v >= iB; --v) ps.st(v + 1, ps.ld(v));
+            ps.st(iB, Vtx<R>{fv.x, fv.y, fv.z, sB.tb});
+            ln.S += fxs(sA.tb) + fxs(sB.tb) - fxs(ps.w(iA));
+            ps.stw(iA, sA.tb);
+            ln.L += fxl(sA.len) + fxl(sB.len) - fxl(AB.len);
+            ln.lp += (double)dlp;
+            ln.n = n + 1;
+        } else {
+            ln.S += fxs(AB.tb) - fxs(ps.w(iA)) - fxs(ps.w(jv));
+            for (int v = jv; v <= n - 2; ++v) ps.st(v, ps.ld(v + 1));
+            ps.stw(iA, AB.tb);
+            ln.L -= fxl(sA.len) + fxl(sB.len) - fxl(AB.len);
+            ln.lp -= (double)dlp;
+            ln.n = n - 1;
+        }
+        ln.invw = sc.logw ? exp(-sc.logw[ln.n]) : 1.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The step kernel.  TAB: stage the media tables in LDS.
+// ---------------------------------------------------------------------------
+template <class R, bool TAB, bool MALA>
+__global__ void __launch_bounds__(256) run_kernel(KArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int tid = threadIdx.x, bs = blockDim.x;
+    MedTab<R> tab = hbm_tab<R>(a);
+    size_t tab_bytes = 0;
+    if (TAB) {
+        // layer table, then edges, then prefix integrals, each 16-byte aligned
+        const size_t nl = (size_t)a.L_total * LY_NW, ne = (size_t)a.n_edges;
+        R* lay = (R*)smem;
+        double* edge = (double*)(smem + ((nl * sizeof(R) + 15) & ~(size_t)15));
+        double* pre = edge + ((ne + 1) & ~(size_t)1);
+        for (size_t i = tid; i < nl; i += bs) lay[i] = ((const R*)a.lay)[i];
+        for (size_t i = tid; i < ne; i += bs) edge[i] = a.edge[i];
+        for (size_t i = tid; i < 2 * ne; i += bs) pre[i] = a.pre[i];
+        __syncthreads();
+        tab = MedTab<R>{lay, edge, pre};
+        tab_bytes = a.tab_bytes;
+    }
+    const int c = blockIdx.x * bs + tid;
+    if (c >= a.C) return;
+    const size_t C = (size_t)a.C;
+    Vtx<R>* lslots = (Vtx<R>*)(smem + tab_bytes) + tid;
+    const int t = a.target[c];
+    Lane<R> ln{};
+    ln.n = a.n[c];
+    const int cap = a.cap;
+    // malformed chains are flagged and never touched
+    if (t < 0 || t >= a.T || ln.n < 2 || ln.n > cap || a.medium[t] < 0 || a.medium[t] >= a.n_media) {
+        a.status[c] = 1;
+        return;
+    }
+    Tgt<R> T;
+    load_target(a, t, T, tab);
+    PathRef<R, false> ps{lslots, (Vtx<R>*)a.verts + c, bs, a.V, C};
+    PathRef<R, true> pl{lslots, (Vtx<R>*)a.verts + c, bs, a.V, C};
+    GlobalPath<R> work{a.work ? (Vtx<R>*)a.work + c : nullptr, C};
+    // stage the LDS part of the path
+    const int nl0 = ln.n < a.V ? ln.n : a.V;
+    for (int v = 0; v < nl0; ++v) ps.lds[v * bs] = ps.glb[(size_t)v * C];
+
+    ln.lp = full_logp(T, ps, ln.n, ln.S, ln.L);
+    const bool healthy = isfinite(ln.lp);
+    a.status[c] = healthy ? 0 : 1;
+
+    StepCtx sc;
+    sc.chain = (uint32_t)c;
+    sc.k0 = (uint32_t)a.seed;
+    sc.k1 = (uint32_t)(a.seed >> 32);
+    sc.cap = cap;
+    sc.bthresh = a.bthresh;
+    const double pb = (double)a.bthresh * 0x1p-32;
+    sc.log_pb = (float)log(pb);
+    sc.log_pd = (float)log1p(-pb);
+    sc.sigma = a.sigma;
+    sc.kappa = a.kappa_end;
+    sc.e2k = exp(-2.0 * a.kappa_end);
+    sc.mala_h = a.mala_h;
+    sc.sampler = a.sampler;
+    sc.logw = a.logw ? a.logw + (size_t)t * (cap + 1) : nullptr;
+    ln.invw = sc.logw ? exp(-sc.logw[ln.n]) : 1.0;
+    int phase = (int)(a.step0 % (uint64_t)a.cycle_len);
+
+    for (int s = 0; s < a.steps && healthy; ++s) {
+        const uint64_t step = a.step0 + (uint64_t)s;
+        const bool perturb = phase < a.n_perturb;
+        int move, idx, accepted;
+        R logA, logu;
+        // the LDS-only instantiation when every active lane's path (and a birth) fits its slots
+        if (__all(ln.n < a.V))
+            step_body<R, true, MALA>(T, pl, work, ln, sc, step, perturb, move, idx, accepted, logA, logu);
+        else
+            step_body<R, false, MALA>(T, ps, work, ln, sc, step, perturb, move, idx, accepted, logA, logu);
+        if ((int64_t)step >= a.burn_in) {
+            const int n = ln.n;
+            ln.cnt += 1;
+            ln.a1 += ln.invw;
+            if (n == T.n0) ln.a2 += ln.invw;
+            ln.sl += ln.L;
+            const double Lm = (double)ln.L * 0x1p-32;
+            ln.sl2 += Lm * Lm;
+            ln.sn += n;
+            ln.ncap += (n == cap);
+            if (move == MV_BIRTH) {
+                ln.pb += 1;
+                ln.ab += accepted;
+            } else if (move == MV_DEATH) {
+                ln.pd += 1;
+                ln.ad += accepted;
+            } else {
+                ln.pp += 1;
+                ln.ap += accepted;
+            }
+            if (move == MV_MALA) {
+                ln.mp += 1;
+                ln.ma += accepted;
+            }
+            if (a.hist) atomicAdd(a.hist + (size_t)t * (cap + 1) + n, 1u);
+        }
+        if (a.trace) {
+            double* tr = a.trace + ((size_t)c * a.trace_steps + a.trace_off + s) * RJPATH_TRACE_WORDS;
+            tr[0] = move;
+            tr[1] = accepted;
+            tr[2] = idx;
+            tr[3] = (double)logA;
+            tr[4] = (double)logu;
+        }
+        phase = (phase + 1 == a.cycle_len) ? 0 : phase + 1;
+    }
+
+    // write back the LDS part, the vertex count, log p and the statistics
+    const int nw = ln.n < a.V ? ln.n : a.V;
+    for (int v = 0; v < nw; ++v) ps.glb[(size_t)v * C] = ps.lds[v * bs];
+    a.n[c] = ln.n;
+    a.logp[c] = ln.lp;
+    if (healthy) {
+        double* sp = a.stats + (size_t)c * RJPATH_NSTAT;
+        sp[0] += ln.cnt;
+        sp[1] += ln.a1;
+        sp[2] += ln.a2;
+        sp[3] += (double)ln.sl * 0x1p-32;
+        sp[4] += ln.sl2;
+        sp[5] += ln.sn;
+        sp[6] += ln.pp;
+        sp[7] += ln.pb;
+        sp[8] += ln.pd;
+        sp[9] += ln.ap;
+        sp[10] += ln.ab;
+        sp[11] += ln.ad;
+        sp[12] += ln.ncap;
+        sp[13] += ln.mp;
+        sp[14] += ln.ma;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Score kernel: log p, d log p / d vertices and the per-layer parameter score.
+// ---------------------------------------------------------------------------
+template <class R>
+__global__ void __launch_bounds__(256) grad_kernel(KArgs a, double* logp_out, Vtx<R>* dv, double* score,
+                                                   int L_total) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.C) return;
+    const size_t C = (size_t)a.C;
+    GlobalPath<R> ps{(Vtx<R>*)a.verts + c, C};
+    const int t = a.target[c];
+    const int n = a.n[c];
+    if (t < 0 || t >= a.T || n < 2 || n > a.cap || a.medium[t] < 0 || a.medium[t] >= a.n_media) {
+        if (logp_out) logp_out[c] = __builtin_nan("");
+        return;
+    }
+    Tgt<R> T;
+    load_target(a, t, T, hbm_tab<R>(a));
+    double lp = score_stream(T, ps, n, [&](int k, V3<R> g) {
+        if (dv) dv[(size_t)k * C + c] = Vtx<R>{k > 0 ? g.x : (R)0, k > 0 ? g.y : (R)0, k > 0 ? g.z : (R)0, (R)0};
+    });
+    if (logp_out) logp_out[c] = lp;
+    if (score && isfinite(lp) && a.status[c] == 0) {
+        const int off = a.minfo[a.medium[t]].off;
+        const double* logw = a.logw ? a.logw + (size_t)t * (a.cap + 1) : nullptr;
+        const double iw = logw ? exp(-logw[n]) : 1.0;
+        double* sc = score + (size_t)t * (1 + 3 * (size_t)L_total);
+        atomicAdd(sc, iw);
+        // d/d lambda_s = -b^2 d/db, d/d lambda_a = -a^2 d/da, with d log p/da = -L_l and
+        // d log p/db = N_l / b - L_l (L_l: path length in layer l, N_l: scatterings in l)
+        V3<R> fprev = ps.p(0);
+        Seg<R> sprev;
+        for (int k = 1; k < n; ++k) {
+            V3<R> fc = ps.p(k);
+            Seg<R> s = make_seg(T, fprev, fc);
+            double uP = axis_u(T, fprev), uQ = axis_u(T, fc);
+            int lP = layer_u(T, uP), lQ = layer_u(T, uQ);
+            double lo = uP < uQ ? uP : uQ, hi = uP < uQ ? uQ : uP;
+            int llo = lP < lQ ? lP : lQ, lhi = lP < lQ ? lQ : lP;
+            double scl = lP == lQ ? 0.0 : (double)s.len / (hi - lo);
+            for (int l = llo; l <= lhi; ++l) {
+                double Lin = lP == lQ ? (double)s.len
+                                      : ((l == lhi ? hi : T.edge[l + 1]) - (l == llo ? lo : T.edge[l])) * scl;
+                const LayV<R> ly = lay_at(T, l);
+                double av = (double)ly.a, bv = (double)ly.b;
+                atomicAdd(sc + 1 + 3 * (off + l) + 0, iw * (bv * bv * Lin));
+                atomicAdd(sc + 1 + 3 * (off + l) + 1, iw * (av * av * Lin));
+            }
+            if (k >= 2) {
+                int l = layer_at(T, fprev);
+                const LayV<R> ly = lay_at(T, l);
+                double bv = (double)ly.b, g = (double)ly.g, fsl = (double)ly.fsl;
+                V3<R> dd = sprev.u - s.u;
+                double q = (double)dot(dd, dd);
+                double mu = 1.0 - 0.5 * q;
+                double den = (1 - g) * (1 - g) + g * q;
+                double dhg = -2 * g / (1 - g * g) - 3 * (g - mu) / den;
+                double dg = dhg;
+                if (fsl != 0.0) {
+                    const double PI = 3.14159265358979323846;
+                    double lhg = log((1 - g * g) / (4 * PI)) - 1.5 * log(den);
+                    double lsl = log((1 + g) / (1 - g) / (4 * PI)) + 2 * g / (1 - g) * log(0.5 * (1 + mu));
+                    double dsl = 2.0 / ((1 + g) * (1 - g)) + 2.0 / ((1 - g) * (1 - g)) * log(0.5 * (1 + mu));
+                    double m = lhg > lsl ? lhg : lsl;
+                    double es = fsl * exp(lsl - m), eh = (1 - fsl) * exp(lhg - m);
+                    dg = (es * dsl + eh * dhg) / (es + eh);
+                }
+                atomicAdd(sc + 1 + 3 * (off + l) + 0, iw * (-bv)); // log b at a scattering vertex
+                atomicAdd(sc + 1 + 3 * (off + l) + 2, iw * dg);
+            }
+            sprev = s;
+            fprev = fc;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+template <class R, bool TAB, bool MALA> static hipError_t launch_run_t(const KArgs& a, int block, hipStream_t s) {
+    int grid = (a.C + block - 1) / block;
+    size_t lds = (TAB ? a.tab_bytes : 0) + (size_t)a.V * block * sizeof(Vtx<R>);
+    hipLaunchKernelGGL((run_kernel<R, TAB, MALA>), dim3(grid), dim3(block), lds, s, a);
+    return hipGetLastError();
+}
+
+template <class R> static hipError_t launch_run_p(const KArgs& a, int block, hipStream_t s) {
+    const bool mala = a.sampler == RJPATH_MALA;
+    if (a.tab_bytes)
+        return mala ? launch_run_t<R, true, true>(a, block, s) : launch_run_t<R, true, false>(a, block, s);
+    return mala ? launch_run_t<R, false, true>(a, block, s) : launch_run_t<R, false, false>(a, block, s);
+}
+
+hipError_t launch_run(const KArgs& a, int block, hipStream_t s) {
+    return a.prec == RJPATH_F64 ? launch_run_p<double>(a, block, s) : launch_run_p<float>(a, block, s);
+}
+
+hipError_t set_run_lds_limit() {
+    const void* fns[] = {
+        (const void*)run_kernel<float, false, false>,  (const void*)run_kernel<float, true, false>,
+        (const void*)run_kernel<double, false, false>, (const void*)run_kernel<double, true, false>,
+        (const void*)run_kernel<float, false, true>,   (const void*)run_kernel<float, true, true>,
+        (const void*)run_kernel<double, false, true>,  (const void*)run_kernel<double, true, true>};
+    for (const void* f : fns) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_grad(const KArgs& a, double* logp_out, void* dv, double* score, int L_total, hipStream_t s) {
+    int block = 256, grid = (a.C + block - 1) / block;
+    if (a.prec == RJPATH_F64)
+        hipLaunchKernelGGL(grad_kernel<double>, dim3(grid), dim3(block), 0, s, a, logp_out, (Vtx<double>*)dv, score,
+                           L_total);
+    else
+        hipLaunchKernelGGL(grad_kernel<float>, dim3(grid), dim3(block), 0, s, a, logp_out, (Vtx<float>*)dv, score,
+                           L_total);
+    return hipGetLastError();
+}
+
+} // namespace rj

@@ -419,3 +419,25 @@ def test_single_scatter_anchor_matches_tracer(oracle_mod):
     m, se, b = orc.trace(0, 20_000_000, esc=300.0)
     assert b[0, 0] == 0.0
     assert abs(b[1, 0] - I3b) < 3.5 * b[1, 1] + 2e-3 * I3b, (b[1], I3b)
+
+
+@pytest.mark.slow
+def test_single_scatter_anchor_layered_matches_tracer(oracle_mod):
+    """Same as above in a layered medium (1 m layers with strongly varying
+    scattering): the radial integral is split at the layer crossings."""
+    w = _layered(oracle_mod, [3.0, 12.0, 5.0, 30.0, 4.0, 8.0], [20.0, 60.0, 15.0, 80.0, 30.0, 50.0], g=0.85, dz=1.0)
+    w["t_src"] = np.array([[0.0, 0.0, 2.3]])
+    ang = math.radians(50)
+    w["t_sensor"] = w["t_src"] + np.array([[1.6, 0.3, -1.1]])
+    w["t_radius"] = np.array([0.3])
+    w["t_emit_kind"] = np.array([W.EMIT_CONE], np.int32)
+    w["t_emit_param"] = np.array([math.radians(25)])
+    w["t_emit_dir"] = np.array([[math.sin(ang), 0.0, math.cos(ang)]])
+    w["t_n0"] = np.array([3], np.int32)
+    orc = oracle_mod.Oracle(w)
+    I3 = orc.anchor_I3(0, 24, 24, 8, 10, 10)
+    I3b = orc.anchor_I3(0, 32, 32, 12, 12, 12)
+    assert I3 == pytest.approx(I3b, rel=2e-3)
+    m, se, b = orc.trace(0, 20_000_000, esc=300.0)
+    assert b[0, 0] == 0.0
+    assert abs(b[1, 0] - I3b) < 3.5 * b[1, 1] + 2e-3 * I3b, (b[1], I3b)
