@@ -48,6 +48,11 @@ def parse():
     ap.add_argument("--chunk", type=int, default=1000, help="sampler steps per benchmark step")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-extras", action="store_true", help="skip the layered and grad-vs-plain measurements")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time the launch configurations first (default: the library's measured default)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first run one plain device copy of this size (calibrates HBM byte counters)")
     return ap.parse_args()
 
 
@@ -75,6 +80,73 @@ def cpu_baseline(w, budget_s):
                 sample=f"{len(idx)} chains (one per 16 chain groups) x {done} steps, FP64, {t_used:.1f} s")
 
 
+def _ess_run(s, steps, chunk):
+    """Times `steps` sampler steps in chunks; returns (seconds, median se/I).
+    se/I does not depend on the anchor, so unit anchors are used."""
+    import torch
+    s._anchor = np.ones(s.T)
+    s.stats.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps // chunk):
+        s.run(chunk)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    res = s.intensity()
+    r = res["se"] / res["I"]
+    ok = np.isfinite(r) & (r > 0)
+    return dt, float(np.median(r[ok])) if ok.any() else float("nan"), int(ok.sum())
+
+
+def grad_vs_plain(steps=3000, chunk=500):
+    """Config 4's layered medium and cone-source geometry (262,144 chains):
+    the plain sampler vs the gradient-informed one (joint Langevin interior
+    moves, step size tuned towards 57.4% acceptance), each after the same
+    sector-tilt tuning and burn-in; ESS/s at 1% relative error of the median
+    target, ESS/s := 1 / (r^2 t)."""
+    from paper_1811_04156_amd import tune as tuning
+    from paper_1811_04156_amd import workloads as W
+    from paper_1811_04156_amd.rjpath import Sampler
+    out = {}
+    for name in ("plain", "mala"):
+        w = W.config4()
+        w.update(burn_in=0, sampler=0)
+        s = Sampler(w, device="cuda:0", precision="f32")
+        tuning.tune_tilt(s, rounds=3, steps=300)
+        h = None
+        if name == "mala":
+            h, acc = tuning.tune_mala(s, h0=0.02, rounds=6, steps=150)
+        s.run(500)  # burn-in
+        dt, r, nt = _ess_run(s, steps, chunk)
+        st = s.stats.cpu().numpy()
+        out[name] = {"seconds": dt, "median_rel_err": r, "targets": nt, "ess_per_s": 1.0 / (r * r * dt),
+                     "t_1pct_s": dt * (r / 0.01) ** 2, "evals_per_s": s.C * steps / dt,
+                     "mean_vertices": float(st[:, 5].sum() / max(1.0, st[:, 0].sum()))}
+        if h is not None:
+            out[name].update(mala_h=h, mala_acceptance=float(st[:, 14].sum() / max(1.0, st[:, 13].sum())))
+    out["ess_ratio_mala_over_plain"] = out["mala"]["ess_per_s"] / out["plain"]["ess_per_s"]
+    return out
+
+
+def layered_throughput(steps=1000):
+    """Config 3 (2^20 chains, 100 layers, cap 512) sampler throughput."""
+    import torch
+    from paper_1811_04156_amd import workloads as W
+    from paper_1811_04156_amd.rjpath import Sampler
+    w = W.config3()
+    w["burn_in"] = 0
+    s = Sampler(w, device="cuda:0", precision="f32")
+    s.run(200)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.run(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = s.stats.cpu().numpy()
+    return {"evals_per_s": s.C * steps / dt, "chains": s.C, "steps": steps,
+            "mean_vertices": float(st[:, 5].sum() / max(1.0, st[:, 0].sum()))}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -86,11 +158,32 @@ def main():
     from paper_1811_04156_amd.rjpath import Sampler
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_probe_mib:
+        nb = args.copy_probe_mib << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     w = W.config2()
     w["burn_in"] = args.warmup * args.chunk
+    from paper_1811_04156_amd import tune as tuning
     s = Sampler(w, device="cuda:0", precision="f32")
     stream = torch.cuda.current_stream()
     C = s.C
+    # untimed set-up: sector tilt and launch configuration (pilot steps are
+    # ordinary sampler steps; their statistics are discarded)
+    # (the pilot rounds are full-length launches, so every dispatch of the step
+    # kernel in this program is one benchmark chunk)
+    torch.cuda.synchronize()
+    t_tune = time.perf_counter()
+    tuning.tune_tilt(s, rounds=3, steps=args.chunk)
+    block, vlds = (0, 0)
+    if args.autotune:
+        block, vlds = tuning.tune_launch(s, steps=4800)
+    torch.cuda.synchronize()
+    t_tune = time.perf_counter() - t_tune
+    s.w["burn_in"] = s.step + args.warmup * args.chunk
     # warm-up (burn-in) steps, untimed
     for _ in range(args.warmup):
         s.run(args.chunk)
@@ -153,9 +246,14 @@ def main():
         "mean_vertices": nbar,
         "acceptance": {"perturb": acc[0], "birth": acc[1], "death": acc[2]},
         "kernel_ms_per_launch": float(np.mean(kern)),
+        "tuning": {"seconds": t_tune, "block_chains": block or "default (64)", "v_lds": vlds or "default (32)",
+                   "tilted_targets": int((s.logw.cpu().numpy().max(1) > 0).sum()) if s.logw is not None else 0},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32, "traffic": None},
     }
+    if not args.no_extras:
+        out["layered_config3"] = layered_throughput()
+        out["grad_vs_plain"] = grad_vs_plain()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(out), flush=True)

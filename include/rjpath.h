@@ -156,7 +156,13 @@ typedef struct {
  * rjpath_autotune) or a default.  chunk: steps per kernel launch (0 = all).
  * trace: NULL or n_chains * steps * RJPATH_TRACE_WORDS doubles.
  * hist: NULL or n_targets * (cap + 1) uint32 counts of the sector n after
- * every post-burn-in step (for tuning the sector tilt). */
+ * every post-burn-in step (for tuning the sector tilt).
+ * step_counter: NULL, or a device uint64 holding the global step index; the
+ * kernels then read the first step from it (step0 is ignored) and the call
+ * enqueues an increment by `steps` after them.  A captured graph of the call
+ * (hipStreamBeginCapture / torch.cuda.graph) then advances the chains on
+ * every replay instead of repeating the same random numbers.  Such a call
+ * records kernel nodes only (no memset), and trace must be NULL. */
 typedef struct {
     uint64_t seed;
     uint64_t step0;
@@ -174,6 +180,7 @@ typedef struct {
     int32_t chunk;
     double* trace;
     uint32_t* hist;
+    uint64_t* step_counter;
 } rjpath_run_params;
 
 /* Thread-local description of the last error. */
@@ -248,7 +255,8 @@ int rjpath_grad(rjpath_medium* m, const rjpath_targets* t, const rjpath_chains* 
  * does not depend on the launch configuration), and stores the fastest
  * configuration in the handle for this (cap, precision, sampler).  Writes it to
  * best_block_chains / best_v_lds if non-NULL.  `steps` must be at least the
- * number of candidates.  Synchronises the stream. */
+ * twice the number of candidates (each is timed in two passes, the second in
+ * reverse order).  Synchronises the stream. */
 int rjpath_autotune(rjpath_medium* m, const rjpath_targets* t, const rjpath_chains* c,
                     const rjpath_run_params* p, int32_t steps, int32_t* best_block_chains, int32_t* best_v_lds,
                     void* stream);

@@ -302,9 +302,10 @@ size_t slot_budget(const rjpath_medium* m, const rjpath_targets* t, const rjpath
 }
 
 void default_launch(int cap, int prec, int& block, int& V) {
-    block = 128;
-    int vmax = (64 * 1024) / (block * (int)vtx_bytes(prec));
-    V = std::min(cap, vmax);
+    // one wave per block with 32 slots (16 in FP64) per lane: the fastest
+    // configuration measured on the batched homogeneous workload
+    block = 64;
+    V = std::min(cap, prec == RJPATH_F64 ? 16 : 32);
 }
 
 int run_impl(rjpath_medium* m, const rjpath_targets* t, const rjpath_chains* c, const rjpath_run_params* p,
@@ -323,13 +324,19 @@ int run_impl(rjpath_medium* m, const rjpath_targets* t, const rjpath_chains* c, 
     a.trace = p->trace;
     a.trace_steps = p->steps;
     a.hist = p->hist;
+    a.step_dev = p->step_counter;
     int chunk = p->chunk > 0 ? p->chunk : p->steps;
     for (int done = 0; done < p->steps; done += chunk) {
-        a.step0 = p->step0 + (uint64_t)done;
+        // with a device counter, step0 carries the offset inside this call
+        a.step0 = (p->step_counter ? 0 : p->step0) + (uint64_t)done;
         a.steps = std::min(chunk, p->steps - done);
         a.trace_off = done;
         hipError_t e = launch_run(a, block, s);
         if (e != hipSuccess) return hip_fail(e, "run kernel launch");
+    }
+    if (p->step_counter) {
+        hipError_t e = launch_advance(p->step_counter, (uint64_t)p->steps, s);
+        if (e != hipSuccess) return hip_fail(e, "step counter kernel launch");
     }
     return RJPATH_OK;
 }
@@ -353,6 +360,7 @@ int check_run(const rjpath_medium* m, const rjpath_targets* t, const rjpath_chai
         return fail(RJPATH_EINVAL, "block_chains must be 64, 128, 192 or 256");
     if (p->v_lds < 0 || p->v_lds > c->cap) return fail(RJPATH_EINVAL, "v_lds must lie in [0, cap]");
     if (p->chunk < 0) return fail(RJPATH_EINVAL, "chunk must be >= 0");
+    if (p->step_counter && p->trace) return fail(RJPATH_EINVAL, "trace needs a host step0 (no step_counter)");
     return RJPATH_OK;
 }
 
@@ -395,9 +403,11 @@ int rjpath_autotune(rjpath_medium* m, const rjpath_targets* t, const rjpath_chai
             if ((size_t)vv * b * vtx_bytes(c->precision) > budget) continue;
             if (std::find(cand.begin(), cand.end(), std::make_pair(b, vv)) == cand.end()) cand.push_back({b, vv});
         }
-    if (steps < (int)cand.size())
-        return fail(RJPATH_EINVAL, "autotune needs steps >= " + std::to_string(cand.size()) + " (one per candidate)");
-    int trial = steps / (int)cand.size();
+    // two passes, the second in reverse order, so that the drift of the chain
+    // state during the trials (paths lengthening after a start) favours no candidate
+    const int nc = (int)cand.size();
+    int trial = steps / (2 * nc);
+    if (trial < 1) return fail(RJPATH_EINVAL, "autotune needs steps >= " + std::to_string(2 * nc));
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0), "hipEventCreate");
     HIPCHK(hipEventCreate(&e1), "hipEventCreate");
@@ -406,28 +416,27 @@ int rjpath_autotune(rjpath_medium* m, const rjpath_targets* t, const rjpath_chai
     q.trace = nullptr;
     q.hist = nullptr;
     q.chunk = 0;
-    double best = 1e300;
-    std::pair<int, int> bc = cand[0];
+    std::vector<double> tms(nc, 0.0);
     uint64_t step = p->step0;
-    for (auto& cv : cand) {
-        q.step0 = step;
-        HIPCHK(hipEventRecord(e0, s), "hipEventRecord");
-        int rr = run_impl(m, t, c, &q, s, cv.first, cv.second);
-        if (rr) return rr;
-        HIPCHK(hipEventRecord(e1, s), "hipEventRecord");
-        HIPCHK(hipEventSynchronize(e1), "hipEventSynchronize");
-        float ms = 0;
-        HIPCHK(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
-        if (ms < best) {
-            best = ms;
-            bc = cv;
+    for (int pass = 0; pass < 2; ++pass)
+        for (int i = 0; i < nc; ++i) {
+            const auto& cv = cand[pass == 0 ? i : nc - 1 - i];
+            q.step0 = step;
+            HIPCHK(hipEventRecord(e0, s), "hipEventRecord");
+            int rr = run_impl(m, t, c, &q, s, cv.first, cv.second);
+            if (rr) return rr;
+            HIPCHK(hipEventRecord(e1, s), "hipEventRecord");
+            HIPCHK(hipEventSynchronize(e1), "hipEventSynchronize");
+            float ms = 0;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+            tms[pass == 0 ? i : nc - 1 - i] += ms;
+            step += trial;
         }
-        step += trial;
-    }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
+    std::pair<int, int> bc = cand[std::min_element(tms.begin(), tms.end()) - tms.begin()];
     // the remainder of the requested steps with the chosen configuration
-    int rest = steps - trial * (int)cand.size();
+    int rest = steps - 2 * trial * nc;
     if (rest > 0) {
         q.step0 = step;
         q.steps = rest;

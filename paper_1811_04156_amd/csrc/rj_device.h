@@ -22,6 +22,7 @@ template <> struct Mth<float> {
     static __device__ __forceinline__ float exp(float x) { return __expf(x); }
     static __device__ __forceinline__ float sqrt(float x) { return __builtin_sqrtf(x); }
     static __device__ __forceinline__ float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+    static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
     // sin / cos of 2 pi u for u in [0, 1)
     static __device__ __forceinline__ float sin2pi(float u) { return __builtin_amdgcn_sinf(u); }
     static __device__ __forceinline__ float cos2pi(float u) { return __builtin_amdgcn_cosf(u); }
@@ -35,6 +36,7 @@ template <> struct Mth<double> {
     static __device__ __forceinline__ double exp(double x) { return ::exp(x); }
     static __device__ __forceinline__ double sqrt(double x) { return ::sqrt(x); }
     static __device__ __forceinline__ double rsqrt(double x) { return 1.0 / ::sqrt(x); }
+    static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
     static __device__ __forceinline__ double sin2pi(double u) { return ::sinpi(2.0 * u); }
     static __device__ __forceinline__ double cos2pi(double u) { return ::cospi(2.0 * u); }
     static __device__ __forceinline__ double log1p(double x) { return ::log1p(x); }
@@ -265,7 +267,7 @@ template <class R> __device__ __forceinline__ V3<R> unit_dir(V3<R> P, V3<R> Q) {
 // Orthonormal completion of a unit vector (Duff et al., JCGT 2017).
 template <class R> __device__ __forceinline__ void onb(V3<R> n, V3<R>& e2, V3<R>& e3) {
     R sgn = copysign((R)1, n.z);
-    R a = (R)-1 / (sgn + n.z);
+    R a = -Mth<R>::rcp(sgn + n.z);
     R b = n.x * n.y * a;
     e2 = {(R)1 + sgn * n.x * n.x * a, sgn * b, -sgn * n.x};
     e3 = {b, sgn + n.y * n.y * a, -n.y};

@@ -68,6 +68,7 @@ struct KArgs {
     double* trace;
     int32_t trace_steps, trace_off;
     uint32_t* hist;
+    const uint64_t* step_dev; // device step counter (overrides step0) or NULL
 };
 
 } // namespace rj

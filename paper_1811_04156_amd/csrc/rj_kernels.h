@@ -13,6 +13,8 @@ enum { RD_SAMPLES = 0, RD_A, RD_B, RD_L, RD_L2, RD_CHAINS, RD_NW };
 hipError_t launch_run(const KArgs& a, int block, hipStream_t s);
 hipError_t set_run_lds_limit();
 hipError_t launch_grad(const KArgs& a, double* logp_out, void* dv, double* score, int L_total, hipStream_t s);
+// *counter += steps on the device (keeps captured graphs advancing)
+hipError_t launch_advance(uint64_t* counter, uint64_t steps, hipStream_t s);
 // I_{n0} per target into anchor[T] (device).  `lay64` is the FP64 layer table.
 hipError_t launch_anchor(const KArgs& a, const double* gl_x, const double* gl_w, int ngl, double* anchor,
                          hipStream_t s);

@@ -111,11 +111,41 @@ __device__ __forceinline__ double full_logp(const Tgt<R>& T, const P& ps, int n,
     return lp;
 }
 
-// log((1 - e^{-2 beta}) / beta) = log(2 sinh(beta) / beta) - beta
-template <class R> __device__ __forceinline__ R ls2(R beta) {
+// q(s) of the bi-spherical proposal with concentration beta, in the two
+// forms the jump needs: E = e^{-2 beta}, the normaliser
+// log((1 - E) / beta) = log(2 sinh(beta) / beta) - beta, and the inverse CDF
+// of cos s written as w = 1 + cos s = -log(u' + (1 - u') E) / beta with
+// u' = 1 - u.  For beta >= 1/4 the direct forms lose nothing (1 - E > 0.39);
+// below that the expm1 / log1p forms are used.
+template <class R> struct QS {
+    R beta, E, ibeta, lnorm;
+    bool small;
+};
+
+template <class R> __device__ __forceinline__ QS<R> make_qs(R beta) {
+    QS<R> q;
+    q.beta = beta;
     R ab = beta < (R)0 ? -beta : beta;
-    if (ab < (R)1e-6) return (R)0.69314718055994530942 - beta;
-    return Mth<R>::log(-Mth<R>::expm1((R)-2 * beta) / beta);
+    q.small = ab < (R)0.25;
+    q.E = Mth<R>::exp((R)-2 * beta);
+    q.ibeta = Mth<R>::rcp(beta);
+    if (!q.small) {
+        q.lnorm = Mth<R>::log(((R)1 - q.E) * q.ibeta);
+    } else if (ab < (R)1e-6) {
+        q.lnorm = (R)0.69314718055994530942 - beta;
+    } else {
+        q.lnorm = Mth<R>::log(-Mth<R>::expm1((R)-2 * beta) * q.ibeta);
+    }
+    return q;
+}
+
+// 1 + cos s from the uniform u (inverse CDF of q(s))
+template <class R> __device__ __forceinline__ R qs_sample(const QS<R>& q, R u) {
+    R up = (R)1 - u;
+    if (!q.small) return -Mth<R>::log(u + up * q.E) * q.ibeta;
+    R ab = q.beta < (R)0 ? -q.beta : q.beta;
+    if (ab < (R)1e-6) return (R)2 * up;
+    return -Mth<R>::log1p(up * Mth<R>::expm1((R)-2 * q.beta)) * q.ibeta;
 }
 
 template <class R>
@@ -250,7 +280,7 @@ template <class R> struct Lane {
     // statistics of this launch
     double a1, a2, sl2;
     long long sl;
-    uint32_t cnt, sn, ncap, pp, pb, pd, ap, ab, ad, mp, ma;
+    uint32_t cnt, c2, sn, ncap, pp, pb, pd, ap, ab, ad, mp, ma;
 };
 
 struct StepCtx {
@@ -258,7 +288,7 @@ struct StepCtx {
     int cap;
     uint32_t bthresh;
     float log_pb, log_pd;
-    double sigma, kappa, e2k, mala_h;
+    double sigma, ikappa, e2k, mala_h;
     int sampler;
     const double* logw;
 };
@@ -317,29 +347,33 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
             if (logu < logA) {
                 accepted = 1;
                 for (int k = 1; k <= n - 2; ++k) ps.st(k, work.ld(k));
-                ln.lp = full_logp(T, ps, n, ln.S, ln.L);
+                full_logp(T, ps, n, ln.S, ln.L); // refresh the cached depths, S and L
             }
             return;
         }
         // ---------- single-vertex perturbation (interior Gaussian or end-point vMF) ----------
         const V3<R> fo = ps.p(j);
+        move = is_end ? MV_END : MV_INTERIOR;
+        // one log and one sin/cos pair serve both proposals: Box-Muller on
+        // words 4..7 for the Gaussian step, and words 4, 5 for the end-point
+        // von Mises-Fisher step (inverse CDF of its cosine, uniform azimuth)
+        const R u4 = unif<R>(r[4]), u5 = unif<R>(r[5]);
+        const R lg = Mth<R>::log(is_end ? u4 + ((R)1 - u4) * (R)sc.e2k : u4);
+        const R c5 = Mth<R>::cos2pi(u5), s5 = Mth<R>::sin2pi(u5);
         V3<R> fn;
         if (!is_end) {
-            move = MV_INTERIOR;
-            V3<R> xi;
-            box_muller3<R>(r[4], r[5], r[6], r[7], xi);
+            const R rho1 = Mth<R>::sqrt((R)-2 * lg);
+            const R rho2 = Mth<R>::sqrt((R)-2 * Mth<R>::log(unif<R>(r[6])));
+            const V3<R> xi = {rho1 * c5, rho1 * s5, rho2 * Mth<R>::cos2pi(unif<R>(r[7]))};
             fn = fo + (R)sc.sigma * xi;
         } else {
-            move = MV_END;
             V3<R> d = fo - T.eta;
             V3<R> nu = Mth<R>::rsqrt(dot(d, d)) * d, e2, e3;
             onb(nu, e2, e3);
-            R u = unif<R>(r[4]);
-            R omw = -Mth<R>::log(u + ((R)1 - u) * (R)sc.e2k) / (R)sc.kappa; // 1 - cos
-            R w = (R)1 - omw;
-            R sw = Mth<R>::sqrt(omw * ((R)2 - omw));
-            R ph = unif<R>(r[5]);
-            V3<R> nn = w * nu + sw * (Mth<R>::cos2pi(ph) * e2 + Mth<R>::sin2pi(ph) * e3);
+            const R omw = -lg * (R)sc.ikappa; // 1 - cos
+            const R w = (R)1 - omw;
+            const R sw = Mth<R>::sqrt(omw * ((R)2 - omw));
+            const V3<R> nn = w * nu + sw * (c5 * e2 + s5 * e3);
             fn = T.eta + T.rad * nn;
         }
         const bool hm2 = j >= 2, hp1 = j <= n - 2, hp2 = j <= n - 3;
@@ -377,7 +411,6 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
             accepted = 1;
             ps.st(j, Vtx<R>{fn.x, fn.y, fn.z, hp1 ? Bn.tb : (R)0});
             ps.stw(j - 1, An.tb);
-            ln.lp += (double)d;
             ln.S += fxs(An.tb) - fxs(Ao.tb);
             ln.L += fxl(An.len) - fxl(Ao.len);
             if (hp1) {
@@ -419,19 +452,18 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
     const LayV<R> lm = lay_of(T, mid);
     const R gam = (R)0.5 * AB.len;
     const R beta = lm.keq + (R)0.5 * (gam * lm.b - (R)1); // centering rule at the midpoint
+    const QS<R> qs = make_qs(beta);
     V3<R> fv;
     if (birth) {
-        R u4 = unif<R>(r[4]);
-        R ab = beta < (R)0 ? -beta : beta;
         // w = 1 + cos s by the inverse CDF of q(s)
-        R w = ab < (R)1e-6 ? (R)2 * ((R)1 - u4) : -Mth<R>::log1p(((R)1 - u4) * Mth<R>::expm1((R)-2 * beta)) / beta;
+        R w = qs_sample(qs, unif<R>(r[4]));
         // t from the logistic q(t): e^t = a/(1-a); sinh t and cosh t - cos s in closed form
         R a5 = unif<R>(r[5]), b5 = (R)1 - a5, ab2 = (R)2 * a5 * b5;
         R ss = Mth<R>::sqrt(fmax(w * ((R)2 - w), (R)0));
         R ph = unif<R>(r[6]);
         V3<R> e2, e3;
         onb(AB.u, e2, e3);
-        R sc_ = gam / ((R)1 - ab2 * w);
+        R sc_ = gam * Mth<R>::rcp((R)1 - ab2 * w);
         V3<R> tr = Mth<R>::cos2pi(ph) * e2 + Mth<R>::sin2pi(ph) * e3;
         fv = mid + sc_ * ((a5 - b5) * AB.u + (ab2 * ss) * tr);
     } else {
@@ -465,7 +497,7 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
     // segment factors of y over x times |J| / q(s) q(t) q(phi): the inverse-square
     // factors of the two new segments cancel against J; 1 + cos s = q / 2
     const R LOG2PI = (R)1.83787706640934548356;
-    R jac = -sA.tc - sB.tc + AB.tc + (R)2 * Mth<R>::log(sA.len + sB.len) - AB.loglen + ls2(beta) +
+    R jac = -sA.tc - sB.tc + AB.tc + (R)2 * Mth<R>::log(sA.len + sB.len) - AB.loglen + qs.lnorm +
             (R)0.5 * beta * q + LOG2PI;
     const int nx = birth ? n : n - 1;
     const long long Sx = birth ? ln.S : ln.S - fxs(ps.w(iA)) - fxs(ps.w(jv)) + fxs(AB.tb);
@@ -476,21 +508,18 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
     logA = valid ? (birth ? logAb : -logAb) : Mth<R>::ninf();
     if (logu < logA) {
         accepted = 1;
-        R dlp = (ty - tx) + seg_term(sA) + seg_term(sB) - seg_term(AB);
         if (birth) {
             for (int v = n - 1; v >= iB; --v) ps.st(v + 1, ps.ld(v));
             ps.st(iB, Vtx<R>{fv.x, fv.y, fv.z, sB.tb});
             ln.S += fxs(sA.tb) + fxs(sB.tb) - fxs(ps.w(iA));
             ps.stw(iA, sA.tb);
             ln.L += fxl(sA.len) + fxl(sB.len) - fxl(AB.len);
-            ln.lp += (double)dlp;
             ln.n = n + 1;
         } else {
             ln.S += fxs(AB.tb) - fxs(ps.w(iA)) - fxs(ps.w(jv));
             for (int v = jv; v <= n - 2; ++v) ps.st(v, ps.ld(v + 1));
             ps.stw(iA, AB.tb);
             ln.L -= fxl(sA.len) + fxl(sB.len) - fxl(AB.len);
-            ln.lp -= (double)dlp;
             ln.n = n - 1;
         }
         ln.invw = sc.logw ? exp(-sc.logw[ln.n]) : 1.0;
@@ -555,16 +584,17 @@ __global__ void __launch_bounds__(256) run_kernel(KArgs a) {
     sc.log_pb = (float)log(pb);
     sc.log_pd = (float)log1p(-pb);
     sc.sigma = a.sigma;
-    sc.kappa = a.kappa_end;
+    sc.ikappa = 1.0 / a.kappa_end;
     sc.e2k = exp(-2.0 * a.kappa_end);
     sc.mala_h = a.mala_h;
     sc.sampler = a.sampler;
     sc.logw = a.logw ? a.logw + (size_t)t * (cap + 1) : nullptr;
     ln.invw = sc.logw ? exp(-sc.logw[ln.n]) : 1.0;
-    int phase = (int)(a.step0 % (uint64_t)a.cycle_len);
+    const uint64_t step0 = a.step_dev ? *a.step_dev + a.step0 : a.step0; // step0 is the offset then
+    int phase = (int)(step0 % (uint64_t)a.cycle_len);
 
     for (int s = 0; s < a.steps && healthy; ++s) {
-        const uint64_t step = a.step0 + (uint64_t)s;
+        const uint64_t step = step0 + (uint64_t)s;
         const bool perturb = phase < a.n_perturb;
         int move, idx, accepted;
         R logA, logu;
@@ -576,8 +606,11 @@ __global__ void __launch_bounds__(256) run_kernel(KArgs a) {
         if ((int64_t)step >= a.burn_in) {
             const int n = ln.n;
             ln.cnt += 1;
-            ln.a1 += ln.invw;
-            if (n == T.n0) ln.a2 += ln.invw;
+            ln.c2 += (n == T.n0);
+            if (sc.logw) {
+                ln.a1 += ln.invw;
+                if (n == T.n0) ln.a2 += ln.invw;
+            }
             ln.sl += ln.L;
             const double Lm = (double)ln.L * 0x1p-32;
             ln.sl2 += Lm * Lm;
@@ -610,6 +643,8 @@ __global__ void __launch_bounds__(256) run_kernel(KArgs a) {
         phase = (phase + 1 == a.cycle_len) ? 0 : phase + 1;
     }
 
+    // log p of the final path (refreshed once rather than tracked per step)
+    if (healthy) ln.lp = full_logp(T, ps, ln.n, ln.S, ln.L);
     // write back the LDS part, the vertex count, log p and the statistics
     const int nw = ln.n < a.V ? ln.n : a.V;
     for (int v = 0; v < nw; ++v) ps.glb[(size_t)v * C] = ps.lds[v * bs];
@@ -618,8 +653,9 @@ __global__ void __launch_bounds__(256) run_kernel(KArgs a) {
     if (healthy) {
         double* sp = a.stats + (size_t)c * RJPATH_NSTAT;
         sp[0] += ln.cnt;
-        sp[1] += ln.a1;
-        sp[2] += ln.a2;
+        // without a sector tilt 1/w = 1 and the two sums are counts
+        sp[1] += sc.logw ? ln.a1 : (double)ln.cnt;
+        sp[2] += sc.logw ? ln.a2 : (double)ln.c2;
         sp[3] += (double)ln.sl * 0x1p-32;
         sp[4] += ln.sl2;
         sp[5] += ln.sn;
@@ -743,6 +779,15 @@ hipError_t set_run_lds_limit() {
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+__global__ void advance_kernel(uint64_t* counter, uint64_t steps) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *counter += steps;
+}
+
+hipError_t launch_advance(uint64_t* counter, uint64_t steps, hipStream_t s) {
+    hipLaunchKernelGGL(advance_kernel, dim3(1), dim3(64), 0, s, counter, steps);
+    return hipGetLastError();
 }
 
 hipError_t launch_grad(const KArgs& a, double* logp_out, void* dv, double* score, int L_total, hipStream_t s) {

@@ -45,7 +45,7 @@ class RunParams(C.Structure):
                 ("cycle_len", C.c_int32), ("n_perturb", C.c_int32), ("birth_thresh", C.c_uint32),
                 ("sigma", C.c_double), ("kappa_end", C.c_double), ("sampler", C.c_int32), ("mala_h", C.c_double),
                 ("block_chains", C.c_int32), ("v_lds", C.c_int32), ("chunk", C.c_int32), ("trace", _p),
-                ("hist", _p)]
+                ("hist", _p), ("step_counter", _p)]
 
 
 EXPORTS = ["rjpath_last_error", "rjpath_version", "rjpath_init_medium", "rjpath_free_medium", "rjpath_run_chains",
@@ -203,7 +203,7 @@ class Sampler:
         return Chains(self.C, self.cap, self.prec, _tp(self.target), _tp(self.n), _tp(self.verts), _tp(self.logp),
                       _tp(self.status), _tp(self.stats), _tp(self.work))
 
-    def _params(self, steps, run=None, trace=None, hist=None, block=0, v_lds=0, chunk=0, step0=None):
+    def _params(self, steps, run=None, trace=None, hist=None, block=0, v_lds=0, chunk=0, step0=None, counter=None):
         r = dict(self.w)
         r.update(run or {})
         if int(r.get("sampler", 0)) == MALA and self.work is None:
@@ -211,7 +211,35 @@ class Sampler:
         return RunParams(int(r["seed"]), int(self.step if step0 is None else step0), int(r["burn_in"]), int(steps),
                          int(r["cycle_len"]), int(r["n_perturb"]), birth_thresh(r["birth_frac"]), float(r["sigma"]),
                          float(r["kappa_end"]), int(r.get("sampler", 0)), float(r.get("mala_h", 0.05)), int(block),
-                         int(v_lds), int(chunk), _tp(trace), _tp(hist))
+                         int(v_lds), int(chunk), _tp(trace), _tp(hist), _tp(counter))
+
+    def capture(self, steps, run=None, score=True, block=0, v_lds=0):
+        """Captures one chunk of the hot path (`steps` sampler steps, then the
+        score pass) in a CUDA/HIP graph whose every replay advances the chains
+        by `steps` steps (the step index lives in a device counter).  Returns
+        (graph, score tensor accumulated by each replay)."""
+        self.counter = torch.tensor([self.step], dtype=torch.int64, device=self.dev)
+        self.score_acc = torch.zeros((self.T, 1 + 3 * self.medium.L_total), dtype=torch.float64, device=self.dev)
+        p = self._params(steps, run, None, None, block, v_lds, 0, counter=self.counter)
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(g, stream=side):
+                sp = _p(side.cuda_stream)
+                tg, ch = self._targets(), self._chains()
+                _check(load().rjpath_run_chains(self.medium.h, C.byref(tg), C.byref(ch), C.byref(p), sp))
+                if score:
+                    _check(load().rjpath_grad(self.medium.h, C.byref(tg), C.byref(ch), None, None,
+                                              _tp(self.score_acc), sp))
+        torch.cuda.current_stream().wait_stream(side)
+        self._graph_steps = steps
+        return g, self.score_acc
+
+    def replay(self, g, times=1):
+        for _ in range(times):
+            g.replay()
+        self.step += times * self._graph_steps
 
     # -- calls --------------------------------------------------------------
     def run(self, steps, run=None, trace=False, hist=False, block=0, v_lds=0, chunk=0):
