@@ -18,9 +18,12 @@ namespace rj {
 template <class R> struct Mth;
 
 template <> struct Mth<float> {
-    static __device__ __forceinline__ float log(float x) { return __logf(x); }
-    static __device__ __forceinline__ float exp(float x) { return __expf(x); }
-    static __device__ __forceinline__ float sqrt(float x) { return __builtin_sqrtf(x); }
+    // the hardware log2 / exp2 / sqrt without the library's subnormal range
+    // scaling: arguments and results of the path density never come near
+    // 2^-126 except in degenerate paths whose density is zero anyway
+    static __device__ __forceinline__ float log(float x) { return __builtin_amdgcn_logf(x) * 0.693147180559945309f; }
+    static __device__ __forceinline__ float exp(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896341f); }
+    static __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
     static __device__ __forceinline__ float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
     static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
     // sin / cos of 2 pi u for u in [0, 1)

@@ -30,27 +30,39 @@ namespace rj {
 enum { MV_INTERIOR = 0, MV_END = 1, MV_BIRTH = 2, MV_DEATH = 3, MV_MALA = 4, MV_NULL = 5 };
 
 // Lane-private path storage: slots below V in LDS, the rest in HBM.  LO: the
-// whole path is known to be in LDS.
+// whole path is known to be in LDS.  The LDS side is addressed through an
+// address-space-3 pointer to a 4-vector, so that every access is one ds_*
+// instruction (never a generic flat access).
+template <class R> using L4 = R __attribute__((ext_vector_type(4)));
+template <class R> using LdsPtr = __attribute__((address_space(3))) L4<R>*;
+template <class R> using LdsScalar = __attribute__((address_space(3))) R*;
+
+template <class R> __device__ __forceinline__ Vtx<R> lds_ld(LdsPtr<R> p) {
+    const L4<R> q = *p;
+    return Vtx<R>{q.x, q.y, q.z, q.w};
+}
+template <class R> __device__ __forceinline__ void lds_st(LdsPtr<R> p, const Vtx<R>& x) { *p = L4<R>{x.x, x.y, x.z, x.w}; }
+
 template <class R, bool LO> struct PathRef {
-    Vtx<R>* lds; // this lane's slot 0, stride bs
-    Vtx<R>* glb; // this chain's vertex 0, stride C
+    LdsPtr<R> lds; // this lane's slot 0, stride bs
+    Vtx<R>* glb;   // this chain's vertex 0, stride C
     int bs, V;
     size_t C;
     __device__ __forceinline__ Vtx<R> ld(int v) const {
-        if (LO) return lds[v * bs];
-        return v < V ? lds[v * bs] : glb[(size_t)v * C];
+        if (LO || v < V) return lds_ld<R>(lds + v * bs);
+        return glb[(size_t)v * C];
     }
     __device__ __forceinline__ void st(int v, const Vtx<R>& x) const {
-        if (LO || v < V) lds[v * bs] = x;
+        if (LO || v < V) lds_st<R>(lds + v * bs, x);
         else glb[(size_t)v * C] = x;
     }
     __device__ __forceinline__ V3<R> p(int v) const { return pos(ld(v)); }
     __device__ __forceinline__ R w(int v) const {
-        if (LO) return lds[v * bs].w;
-        return v < V ? lds[v * bs].w : glb[(size_t)v * C].w;
+        if (LO || v < V) return ((LdsScalar<R>)(lds + v * bs))[3];
+        return glb[(size_t)v * C].w;
     }
     __device__ __forceinline__ void stw(int v, R x) const {
-        if (LO || v < V) lds[v * bs].w = x;
+        if (LO || v < V) ((LdsScalar<R>)(lds + v * bs))[3] = x;
         else glb[(size_t)v * C].w = x;
     }
 };
@@ -63,35 +75,15 @@ template <class R> struct GlobalPath {
     __device__ __forceinline__ void stw(int, R) const {}
 };
 
-// Fixed-point images (x * 2^bits, truncated) of the cached segment scattering
-// depths (2^40) and lengths (2^32).  Integer sums are associative, so a sum
-// kept by incremental updates equals a fresh re-summation bit for bit and a
-// chain's trajectory does not depend on where launches start and end.  The
-// FP32 form works on the bit pattern (no FP64 conversion).
-__device__ __forceinline__ long long fxb(float x, int bits) {
-    uint32_t u = __float_as_uint(x);
-    int e = (int)((u >> 23) & 0xffu);
-    if (e == 0 || (u >> 31)) return 0; // zero, subnormal (below 2^-126) or negative
-    uint64_t m = (uint64_t)((u & 0x7fffffu) | 0x800000u);
-    int s = e - 150 + bits; // value = m * 2^(e - 150)
-    s = s > 39 ? 39 : s;
-    return (long long)(s >= 0 ? (m << s) : (s > -64 ? (m >> -s) : 0));
-}
-__device__ __forceinline__ long long fxb(double x, int bits) { return (long long)(x * ldexp(1.0, bits)); }
-template <class R> __device__ __forceinline__ long long fxs(R x) { return fxb(x, 40); }
-template <class R> __device__ __forceinline__ long long fxl(R x) { return fxb(x, 32); }
-
 // Full log p of the path (FP64 sum of the factors), refreshing the cached
-// segment scattering depths; also returns S = sum tau_b and the length L
-// (fixed point).
+// segment scattering depths; also returns the path length L.
 template <class R, class P>
-__device__ __forceinline__ double full_logp(const Tgt<R>& T, const P& ps, int n, long long& S, long long& L) {
+__device__ __forceinline__ double full_logp(const Tgt<R>& T, const P& ps, int n, double& L) {
     V3<R> f0 = ps.p(0), f1 = ps.p(1);
     Seg<R> s = make_seg(T, f0, f1);
     bool zero = !(s.len > (R)0);
     double lp = (double)emit_term(T, s.u) + (double)seg_term(s);
-    S = fxs(s.tb);
-    L = fxl(s.len);
+    L = (double)s.len;
     ps.stw(0, s.tb);
     V3<R> fc = f1;
     for (int k = 1; k <= n - 2; ++k) {
@@ -100,8 +92,7 @@ __device__ __forceinline__ double full_logp(const Tgt<R>& T, const P& ps, int n,
         zero |= !(s2.len > (R)0);
         const LayV<R> ly = lay_of(T, fc);
         lp += (double)(ly.logb + turn_term(ly, s.u, s2.u)) + (double)seg_term(s2);
-        S += fxs(s2.tb);
-        L += fxl(s2.len);
+        L += (double)s2.len;
         ps.stw(k, s2.tb);
         s = s2;
         fc = fn;
@@ -270,16 +261,64 @@ __device__ __forceinline__ double score_stream(const Tgt<R>& T, const P& ps, int
 }
 
 // ---------------------------------------------------------------------------
+// One factor of the path density attached to one vertex (App. "Path
+// probability distribution"), evaluated branch-free so that lanes of a wave
+// whose vertices play different roles do not diverge:
+//   VK_EMIT: the source, log eps(ub) of the first direction;
+//   VK_TURN: an interior vertex, log b + log sigma_sr(ua . ub);
+//   VK_END:  the end point fe, log max(0, -ua . nu) + log rho(nu);
+//   VK_NONE: no vertex (0).
+// CE / CT / CN: whether the kinds END / EMIT / NONE can occur at the call.
+// ---------------------------------------------------------------------------
+enum { VK_EMIT = 0, VK_TURN = 1, VK_END = 2, VK_NONE = 3 };
+
+template <class R> __device__ __forceinline__ R rho_log(const Tgt<R>& T, V3<R> nu) {
+    if (T.dk != RJPATH_DET_PAPER) return (R)0;
+    R cr = dot(nu, T.dd);
+    R z = (R)2 * cr + (R)0.7;
+    R az = z < (R)0 ? -z : z;
+    // log rho = 3 c - 1 - log cosh(2 c + 0.7), log cosh z = |z| + log1p(e^{-2|z|}) - log 2
+    return (R)3 * cr - (R)1 - (az + Mth<R>::log1p(Mth<R>::exp((R)-2 * az)) - (R)0.69314718055994530942);
+}
+
+template <class R, bool CE, bool CT, bool CN>
+__device__ __forceinline__ R vtx_term(const Tgt<R>& T, int kind, const LayV<R>& ly, V3<R> ua, V3<R> ub, V3<R> fe) {
+    V3<R> d = ua - ub;
+    R X = ly.hg1 + ly.g * dot(d, d); // HG denominator, 1 - mu = |ua - ub|^2 / 2
+    V3<R> nu = {(R)0, (R)0, (R)0};
+    R ce = (R)1;
+    if (CE) {
+        V3<R> de = fe - T.eta;
+        nu = Mth<R>::rsqrt(dot(de, de)) * de;
+        ce = -dot(ua, nu);
+        if (kind == VK_END) X = ce;
+    }
+    const R lx = Mth<R>::log(X);
+    R turn = ly.logb + ly.hgn - (R)1.5 * lx;
+    if (ly.fsl != (R)0) {
+        R q = dot(d, d);
+        R hg = ly.hgn - (R)1.5 * lx;
+        R sl = ly.sln + ly.sla * Mth<R>::log((R)1 - (R)0.25 * q);
+        R m = sl > hg ? sl : hg;
+        turn = ly.logb + m + Mth<R>::log(ly.fsl * Mth<R>::exp(sl - m) + ((R)1 - ly.fsl) * Mth<R>::exp(hg - m));
+    }
+    R out = turn;
+    if (CE && kind == VK_END) out = ce > (R)0 ? lx + rho_log(T, nu) : Mth<R>::ninf();
+    if (CT && kind == VK_EMIT) out = emit_term(T, ub);
+    if (CN && kind == VK_NONE) out = (R)0;
+    return out;
+}
+
+// ---------------------------------------------------------------------------
 // Per-lane sampler state and statistics.
 // ---------------------------------------------------------------------------
 template <class R> struct Lane {
     int n;
-    long long S, L; // fixed-point sum of cached depths and path length
-    double lp;      // cached log p (refreshed at launch start)
-    double invw;    // 1 / w(n)
+    double L;    // path length (running sum; refreshed at launch start)
+    double lp;   // log p (refreshed at launch start and end)
+    double invw; // 1 / w(n)
     // statistics of this launch
-    double a1, a2, sl2;
-    long long sl;
+    double a1, a2, sl, sl2;
     uint32_t cnt, c2, sn, ncap, pp, pb, pd, ap, ab, ad, mp, ma;
 };
 
@@ -313,6 +352,7 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
     idx = -1;
     accepted = 0;
     logA = Mth<R>::ninf();
+    const V3<R> ex = {(R)1, (R)0, (R)0};
     if (perturb) {
         const int j = 1 + pick(r[0], (uint32_t)(n - 1));
         idx = j;
@@ -347,12 +387,18 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
             if (logu < logA) {
                 accepted = 1;
                 for (int k = 1; k <= n - 2; ++k) ps.st(k, work.ld(k));
-                full_logp(T, ps, n, ln.S, ln.L); // refresh the cached depths, S and L
+                full_logp(T, ps, n, ln.L); // refresh the cached depths and L
             }
             return;
         }
-        // ---------- single-vertex perturbation (interior Gaussian or end-point vMF) ----------
-        const V3<R> fo = ps.p(j);
+        // ---------- single-vertex perturbation: the five-vertex window ----------
+        const bool hm2 = j >= 2, hp1 = !is_end, hp2 = j <= n - 3;
+        const V3<R> fm1 = ps.p(j - 1), fo = ps.p(j);
+        // absent neighbours are replaced by harmless stand-ins (loads stay in range)
+        const V3<R> gm2 = ps.p(hm2 ? j - 2 : 0), gp1 = ps.p(hp1 ? j + 1 : 0), gp2 = ps.p(hp2 ? j + 2 : 0);
+        const V3<R> fm2 = hm2 ? gm2 : fm1 - ex;
+        const V3<R> fp1 = hp1 ? gp1 : fo + ex;
+        const V3<R> fp2 = hp2 ? gp2 : fp1 + ex;
         move = is_end ? MV_END : MV_INTERIOR;
         // one log and one sin/cos pair serve both proposals: Box-Muller on
         // words 4..7 for the Gaussian step, and words 4, 5 for the end-point
@@ -361,83 +407,87 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
         const R lg = Mth<R>::log(is_end ? u4 + ((R)1 - u4) * (R)sc.e2k : u4);
         const R c5 = Mth<R>::cos2pi(u5), s5 = Mth<R>::sin2pi(u5);
         V3<R> fn;
-        if (!is_end) {
+        {
             const R rho1 = Mth<R>::sqrt((R)-2 * lg);
             const R rho2 = Mth<R>::sqrt((R)-2 * Mth<R>::log(unif<R>(r[6])));
             const V3<R> xi = {rho1 * c5, rho1 * s5, rho2 * Mth<R>::cos2pi(unif<R>(r[7]))};
-            fn = fo + (R)sc.sigma * xi;
-        } else {
-            V3<R> d = fo - T.eta;
-            V3<R> nu = Mth<R>::rsqrt(dot(d, d)) * d, e2, e3;
+            const V3<R> fg = fo + (R)sc.sigma * xi;
+            V3<R> dd = fo - T.eta;
+            V3<R> nu = Mth<R>::rsqrt(dot(dd, dd)) * dd, e2, e3;
             onb(nu, e2, e3);
             const R omw = -lg * (R)sc.ikappa; // 1 - cos
-            const R w = (R)1 - omw;
-            const R sw = Mth<R>::sqrt(omw * ((R)2 - omw));
-            const V3<R> nn = w * nu + sw * (c5 * e2 + s5 * e3);
-            fn = T.eta + T.rad * nn;
+            const R wv = (R)1 - omw;
+            const R sw = Mth<R>::sqrt(fmax(omw * ((R)2 - omw), (R)0));
+            const V3<R> fv = T.eta + T.rad * (wv * nu + sw * (c5 * e2 + s5 * e3));
+            fn = is_end ? fv : fg;
         }
-        const bool hm2 = j >= 2, hp1 = j <= n - 2, hp2 = j <= n - 3;
-        const V3<R> fm1 = ps.p(j - 1);
         const Seg<R> Ao = make_seg(T, fm1, fo), An = make_seg(T, fm1, fn);
+        const Seg<R> Bo = make_seg(T, fo, fp1), Bn = make_seg(T, fn, fp1);
+        const V3<R> um = unit_dir(fm2, fm1), up = unit_dir(fp1, fp2);
+        const LayV<R> lm1 = lay_of(T, fm1), lo = lay_of(T, fo), lnw = lay_of(T, fn), lp1 = lay_of(T, fp1);
+        const int km1 = hm2 ? VK_TURN : VK_EMIT;
+        const int kj = is_end ? VK_END : VK_TURN;
+        const int kp1 = !hp1 ? VK_NONE : (hp2 ? VK_TURN : VK_END);
         R d = seg_term(An) - seg_term(Ao);
-        Seg<R> Bo, Bn;
-        V3<R> fp1;
-        if (hp1) {
-            fp1 = ps.p(j + 1);
-            Bo = make_seg(T, fo, fp1);
-            Bn = make_seg(T, fn, fp1);
-            d += seg_term(Bn) - seg_term(Bo);
-            const LayV<R> lo = lay_of(T, fo), lnw = lay_of(T, fn);
-            d += (lnw.logb + turn_term(lnw, An.u, Bn.u)) - (lo.logb + turn_term(lo, Ao.u, Bo.u));
-            if (hp2) {
-                V3<R> up = unit_dir(fp1, ps.p(j + 2));
-                const LayV<R> l1 = lay_of(T, fp1);
-                d += turn_term(l1, Bn.u, up) - turn_term(l1, Bo.u, up);
-            } else {
-                d += end_term(T, Bn.u, fp1) - end_term(T, Bo.u, fp1);
-            }
-        } else {
-            d += end_term(T, An.u, fn) - end_term(T, Ao.u, fo);
-        }
-        if (hm2) {
-            V3<R> um = unit_dir(ps.p(j - 2), fm1);
-            const LayV<R> l1 = lay_of(T, fm1);
-            d += turn_term(l1, um, An.u) - turn_term(l1, um, Ao.u);
-        } else {
-            d += emit_term(T, An.u) - emit_term(T, Ao.u);
-        }
+        d += hp1 ? seg_term(Bn) - seg_term(Bo) : (R)0;
+        d += vtx_term<R, false, true, false>(T, km1, lm1, um, An.u, fm1) -
+             vtx_term<R, false, true, false>(T, km1, lm1, um, Ao.u, fm1);
+        d += vtx_term<R, true, false, false>(T, kj, lnw, An.u, Bn.u, fn) -
+             vtx_term<R, true, false, false>(T, kj, lo, Ao.u, Bo.u, fo);
+        d += vtx_term<R, true, false, true>(T, kp1, lp1, Bn.u, up, fp1) -
+             vtx_term<R, true, false, true>(T, kp1, lp1, Bo.u, up, fp1);
         logA = d;
         if (logu < logA) {
             accepted = 1;
             ps.st(j, Vtx<R>{fn.x, fn.y, fn.z, hp1 ? Bn.tb : (R)0});
             ps.stw(j - 1, An.tb);
-            ln.S += fxs(An.tb) - fxs(Ao.tb);
-            ln.L += fxl(An.len) - fxl(Ao.len);
-            if (hp1) {
-                ln.S += fxs(Bn.tb) - fxs(Bo.tb);
-                ln.L += fxl(Bn.len) - fxl(Bo.len);
-            }
+            ln.L += (double)An.len - (double)Ao.len + (hp1 ? (double)Bn.len - (double)Bo.len : 0.0);
         }
         return;
     }
     // ---------- birth / death through the bi-spherical map ----------
     const bool birth = r[2] < sc.bthresh;
     move = birth ? MV_BIRTH : MV_DEATH;
-    const bool valid = birth ? (n < sc.cap && ln.S > 0) : (n > 2);
+    // the tilt values the move can need, fetched early so that their latency
+    // hides behind the proposal arithmetic
+    double lwm = 0.0, lw0 = 0.0, lwp = 0.0;
+    if (sc.logw) {
+        lwm = sc.logw[n - 1];
+        lw0 = sc.logw[n];
+        lwp = sc.logw[n < sc.cap ? n + 1 : n];
+    }
+    // S = sum of the cached segment depths, summed afresh in a fixed order (so
+    // the chain does not depend on where launches start and end).  The first
+    // WB depths are read once into registers (loads issued together) and
+    // serve both the sum and the segment scan.
+    constexpr int WB = 8;
+    R wv[WB];
+#pragma unroll
+    for (int v = 0; v < WB; ++v) wv[v] = ps.w(v < n - 1 ? v : 0);
+    double S = 0.0;
+#pragma unroll
+    for (int v = 0; v < WB; ++v) S += v < n - 1 ? (double)wv[v] : 0.0;
+    for (int v = WB; v < n - 1; ++v) S += (double)ps.w(v);
+    const bool valid = birth ? (n < sc.cap && S > 0.0) : (n > 2);
     int iA = 0, jv = 1;
     if (valid) {
         if (birth) {
-            // segment k with probability tau_b(k) / S: scan of the cached depths
-            const long long tgt = (long long)((double)unif<double>(r[0]) * (double)ln.S);
-            long long cum = 0;
-            int k = n - 2;
-            for (int v = 0; v < n - 1; ++v) {
-                cum += fxs(ps.w(v));
-                if (cum > tgt) {
-                    k = v;
-                    break;
-                }
+            // segment k with probability tau_b(k) / S: the first k whose
+            // cumulative depth exceeds U S, i.e. the number of prefixes that
+            // do not (the cumulative sums never decrease)
+            const double tgt = (double)unif<double>(r[0]) * S;
+            double cum = 0.0;
+            int k = 0;
+#pragma unroll
+            for (int v = 0; v < WB; ++v) {
+                cum += v < n - 1 ? (double)wv[v] : 0.0;
+                k += (v < n - 1 && cum <= tgt) ? 1 : 0;
             }
+            for (int v = WB; v < n - 1; ++v) {
+                cum += (double)ps.w(v);
+                k += cum <= tgt ? 1 : 0;
+            }
+            k = k < n - 2 ? k : n - 2;
             iA = k;
         } else {
             jv = 1 + pick(r[0], (uint32_t)(n - 2));
@@ -446,7 +496,12 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
         idx = birth ? iA : jv;
     }
     const int iB = birth ? iA + 1 : iA + 2;
+    const bool hprev = iA >= 1, hnext = iB + 1 <= n - 1;
     const V3<R> A = ps.p(iA), B = ps.p(iB < n ? iB : n - 1);
+    const V3<R> gprev = ps.p(hprev ? iA - 1 : 0), gnext = ps.p(hnext ? iB + 1 : 0);
+    const V3<R> fprev = hprev ? gprev : A - ex;
+    const V3<R> fnext = hnext ? gnext : B + ex;
+    const V3<R> fj = ps.p(jv);
     const Seg<R> AB = make_seg(T, A, B);
     const V3<R> mid = (R)0.5 * (A + B);
     const LayV<R> lm = lay_of(T, mid);
@@ -454,9 +509,9 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
     const R beta = lm.keq + (R)0.5 * (gam * lm.b - (R)1); // centering rule at the midpoint
     const QS<R> qs = make_qs(beta);
     V3<R> fv;
-    if (birth) {
-        // w = 1 + cos s by the inverse CDF of q(s)
-        R w = qs_sample(qs, unif<R>(r[4]));
+    {
+        // the bi-spherical proposal (used by births; deaths take the vertex itself)
+        R w = qs_sample(qs, unif<R>(r[4])); // 1 + cos s by the inverse CDF of q(s)
         // t from the logistic q(t): e^t = a/(1-a); sinh t and cosh t - cos s in closed form
         R a5 = unif<R>(r[5]), b5 = (R)1 - a5, ab2 = (R)2 * a5 * b5;
         R ss = Mth<R>::sqrt(fmax(w * ((R)2 - w), (R)0));
@@ -465,64 +520,48 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
         onb(AB.u, e2, e3);
         R sc_ = gam * Mth<R>::rcp((R)1 - ab2 * w);
         V3<R> tr = Mth<R>::cos2pi(ph) * e2 + Mth<R>::sin2pi(ph) * e3;
-        fv = mid + sc_ * ((a5 - b5) * AB.u + (ab2 * ss) * tr);
-    } else {
-        fv = ps.p(jv);
+        const V3<R> fb = mid + sc_ * ((a5 - b5) * AB.u + (ab2 * ss) * tr);
+        fv = birth ? fb : fj;
     }
-    const bool hprev = iA >= 1, hnext = iB + 1 <= n - 1;
     const Seg<R> sA = make_seg(T, A, fv), sB = make_seg(T, fv, B);
-    R tx = (R)0, ty = (R)0;
-    if (hprev) {
-        V3<R> up = unit_dir(ps.p(iA - 1), A);
-        const LayV<R> la = lay_of(T, A);
-        tx += turn_term(la, up, AB.u);
-        ty += turn_term(la, up, sA.u);
-    } else {
-        tx += emit_term(T, AB.u);
-        ty += emit_term(T, sA.u);
-    }
-    if (hnext) {
-        V3<R> un = unit_dir(B, ps.p(iB + 1));
-        const LayV<R> lb = lay_of(T, B);
-        tx += turn_term(lb, AB.u, un);
-        ty += turn_term(lb, sB.u, un);
-    } else {
-        tx += end_term(T, AB.u, B);
-        ty += end_term(T, sB.u, B);
-    }
-    const LayV<R> lv = lay_of(T, fv);
+    const V3<R> up = unit_dir(fprev, A), un = unit_dir(B, fnext);
+    const LayV<R> la = lay_of(T, A), lb = lay_of(T, B), lv = lay_of(T, fv);
+    const int kA = hprev ? VK_TURN : VK_EMIT, kB = hnext ? VK_TURN : VK_END;
+    const R tx = vtx_term<R, false, true, false>(T, kA, la, up, AB.u, A) +
+                 vtx_term<R, true, false, false>(T, kB, lb, AB.u, un, B);
+    const R ty = vtx_term<R, false, true, false>(T, kA, la, up, sA.u, A) +
+                 vtx_term<R, true, false, false>(T, kB, lb, sB.u, un, B) +
+                 vtx_term<R, false, false, false>(T, VK_TURN, lv, sA.u, sB.u, fv);
     V3<R> dq = sA.u - sB.u;
     R q = dot(dq, dq);
-    ty += lv.logb + turn_term(lv, sA.u, sB.u);
     // segment factors of y over x times |J| / q(s) q(t) q(phi): the inverse-square
     // factors of the two new segments cancel against J; 1 + cos s = q / 2
     const R LOG2PI = (R)1.83787706640934548356;
     R jac = -sA.tc - sB.tc + AB.tc + (R)2 * Mth<R>::log(sA.len + sB.len) - AB.loglen + qs.lnorm +
             (R)0.5 * beta * q + LOG2PI;
     const int nx = birth ? n : n - 1;
-    const long long Sx = birth ? ln.S : ln.S - fxs(ps.w(iA)) - fxs(ps.w(jv)) + fxs(AB.tb);
-    R lpup = (R)sc.log_pb + Mth<R>::log(AB.tb) - Mth<R>::log((R)((double)Sx * 0x1p-40));
+    const double Sx = birth ? S : S - (double)ps.w(iA) - (double)ps.w(jv) + (double)AB.tb;
+    R lpup = (R)sc.log_pb + Mth<R>::log(AB.tb) - Mth<R>::log((R)Sx);
     R lpdn = (R)sc.log_pd - Mth<R>::log((R)(nx - 1));
-    R dlw = (sc.logw && valid) ? (R)(sc.logw[nx + 1] - sc.logw[nx]) : (R)0;
+    R dlw = (sc.logw && valid) ? (R)(birth ? lwp - lw0 : lw0 - lwm) : (R)0; // logw[nx + 1] - logw[nx]
     R logAb = (ty - tx) + jac + dlw + lpdn - lpup;
     logA = valid ? (birth ? logAb : -logAb) : Mth<R>::ninf();
     if (logu < logA) {
         accepted = 1;
+        const double dL = (double)sA.len + (double)sB.len - (double)AB.len;
         if (birth) {
             for (int v = n - 1; v >= iB; --v) ps.st(v + 1, ps.ld(v));
             ps.st(iB, Vtx<R>{fv.x, fv.y, fv.z, sB.tb});
-            ln.S += fxs(sA.tb) + fxs(sB.tb) - fxs(ps.w(iA));
             ps.stw(iA, sA.tb);
-            ln.L += fxl(sA.len) + fxl(sB.len) - fxl(AB.len);
+            ln.L += dL;
             ln.n = n + 1;
         } else {
-            ln.S += fxs(AB.tb) - fxs(ps.w(iA)) - fxs(ps.w(jv));
             for (int v = jv; v <= n - 2; ++v) ps.st(v, ps.ld(v + 1));
             ps.stw(iA, AB.tb);
-            ln.L -= fxl(sA.len) + fxl(sB.len) - fxl(AB.len);
+            ln.L -= dL;
             ln.n = n - 1;
         }
-        ln.invw = sc.logw ? exp(-sc.logw[ln.n]) : 1.0;
+        ln.invw = sc.logw ? exp(-(birth ? lwp : lwm)) : 1.0;
     }
 }
 
@@ -551,7 +590,7 @@ __global__ void __launch_bounds__(256) run_kernel(KArgs a) {
     const int c = blockIdx.x * bs + tid;
     if (c >= a.C) return;
     const size_t C = (size_t)a.C;
-    Vtx<R>* lslots = (Vtx<R>*)(smem + tab_bytes) + tid;
+    LdsPtr<R> lslots = (LdsPtr<R>)((L4<R>*)(smem + tab_bytes) + tid);
     const int t = a.target[c];
     Lane<R> ln{};
     ln.n = a.n[c];
@@ -568,9 +607,9 @@ __global__ void __launch_bounds__(256) run_kernel(KArgs a) {
     GlobalPath<R> work{a.work ? (Vtx<R>*)a.work + c : nullptr, C};
     // stage the LDS part of the path
     const int nl0 = ln.n < a.V ? ln.n : a.V;
-    for (int v = 0; v < nl0; ++v) ps.lds[v * bs] = ps.glb[(size_t)v * C];
+    for (int v = 0; v < nl0; ++v) lds_st<R>(ps.lds + v * bs, ps.glb[(size_t)v * C]);
 
-    ln.lp = full_logp(T, ps, ln.n, ln.S, ln.L);
+    ln.lp = full_logp(T, ps, ln.n, ln.L);
     const bool healthy = isfinite(ln.lp);
     a.status[c] = healthy ? 0 : 1;
 
@@ -612,8 +651,7 @@ __global__ void __launch_bounds__(256) run_kernel(KArgs a) {
                 if (n == T.n0) ln.a2 += ln.invw;
             }
             ln.sl += ln.L;
-            const double Lm = (double)ln.L * 0x1p-32;
-            ln.sl2 += Lm * Lm;
+            ln.sl2 += ln.L * ln.L;
             ln.sn += n;
             ln.ncap += (n == cap);
             if (move == MV_BIRTH) {
@@ -644,10 +682,10 @@ __global__ void __launch_bounds__(256) run_kernel(KArgs a) {
     }
 
     // log p of the final path (refreshed once rather than tracked per step)
-    if (healthy) ln.lp = full_logp(T, ps, ln.n, ln.S, ln.L);
+    if (healthy) ln.lp = full_logp(T, ps, ln.n, ln.L);
     // write back the LDS part, the vertex count, log p and the statistics
     const int nw = ln.n < a.V ? ln.n : a.V;
-    for (int v = 0; v < nw; ++v) ps.glb[(size_t)v * C] = ps.lds[v * bs];
+    for (int v = 0; v < nw; ++v) ps.glb[(size_t)v * C] = lds_ld<R>(ps.lds + v * bs);
     a.n[c] = ln.n;
     a.logp[c] = ln.lp;
     if (healthy) {
@@ -656,7 +694,7 @@ __global__ void __launch_bounds__(256) run_kernel(KArgs a) {
         // without a sector tilt 1/w = 1 and the two sums are counts
         sp[1] += sc.logw ? ln.a1 : (double)ln.cnt;
         sp[2] += sc.logw ? ln.a2 : (double)ln.c2;
-        sp[3] += (double)ln.sl * 0x1p-32;
+        sp[3] += ln.sl;
         sp[4] += ln.sl2;
         sp[5] += ln.sn;
         sp[6] += ln.pp;
