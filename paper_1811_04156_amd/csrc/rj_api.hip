@@ -81,6 +81,7 @@ struct TuneKey {
 struct rjpath_medium {
     int n_media = 0, L_total = 0, n_edges = 0;
     bool layered = false; // some medium has more than one layer
+    bool has_sl = false;  // some layer has f_SL > 0
     MedInfo* d_info = nullptr;
     double* d_edge = nullptr;
     double* d_pre = nullptr;
@@ -174,6 +175,7 @@ int rjpath_init_medium(rjpath_medium** out, const rjpath_medium_desc* d, void* s
     h->L_total = L;
     h->n_edges = L + M;
     for (int mi = 0; mi < M; ++mi) h->layered |= info[mi].cnt > 1;
+    for (int l = 0; l < L; ++l) h->has_sl |= lay[l * LY_NW + LY_FSL] > 0;
     hipStream_t s = (hipStream_t)stream;
     auto up = [&](void** dst, const void* src, size_t bytes) -> hipError_t {
         hipError_t e = hipMalloc(dst, bytes);
@@ -282,8 +284,10 @@ KArgs make_args(const rjpath_medium* m, const rjpath_targets* t, const rjpath_ch
     a.lay64 = m->d_lay64;
     a.L_total = m->L_total;
     a.n_edges = m->n_edges;
+    a.layered = m->layered;
+    a.has_sl = m->has_sl;
     a.tab_bytes = 0;
-    if (m->layered) {
+    if (m->layered && c->precision == RJPATH_F32) {
         // layer table, edges padded to an even count, prefix pairs (the run kernel's LDS layout)
         size_t lay = ((size_t)m->L_total * LY_NW * (c->precision == RJPATH_F64 ? 8 : 4) + 15) & ~(size_t)15;
         size_t bytes = lay + 8 * (((size_t)m->n_edges + 1) & ~(size_t)1) + 16 * (size_t)m->n_edges;

@@ -115,6 +115,7 @@ template <class R> struct Tgt {
     int n0;       // anchor sector
     // medium
     int mcnt, uniform;
+    bool sl;      // false: no layer of the medium mixes in the Rayleigh-like term
     double ax, ay, az, e0, inv_h, usrc;
     LayV<R> l0;          // layer 0 (the only one of a homogeneous medium)
     const R* lay;        // layer table of this medium (LY_NW per layer), LDS or HBM
@@ -124,7 +125,9 @@ template <class R> struct Tgt {
 
 template <class R> __device__ __forceinline__ LayV<R> lay_at(const Tgt<R>& T, int l) {
     if (T.mcnt == 1) return T.l0;
-    return lay_load(T.lay + l * LY_NW);
+    LayV<R> ly = lay_load(T.lay + l * LY_NW);
+    if (!T.sl) ly.fsl = (R)0;
+    return ly;
 }
 
 template <class R> __device__ __forceinline__ double axis_u(const Tgt<R>& T, V3<R> p) {
@@ -160,7 +163,9 @@ template <class R> __device__ __forceinline__ int layer_at(const Tgt<R>& T, V3<R
 
 template <class R> __device__ __forceinline__ LayV<R> lay_of(const Tgt<R>& T, V3<R> p) {
     if (T.mcnt == 1) return T.l0;
-    return lay_load(T.lay + layer_u(T, axis_u(T, p)) * LY_NW);
+    LayV<R> ly = lay_load(T.lay + layer_u(T, axis_u(T, p)) * LY_NW);
+    if (!T.sl) ly.fsl = (R)0;
+    return ly;
 }
 
 // Optical depths of the segment P -> Q of length len: total c = a + b and
@@ -312,6 +317,7 @@ __device__ __forceinline__ void load_target(const KArgs& a, int t, Tgt<R>& T, co
     T.n0 = a.n0[t];
     const MedInfo mi = a.minfo[a.medium[t]];
     T.mcnt = mi.cnt;
+    T.sl = true;
     T.uniform = mi.uniform;
     T.ax = mi.ax;
     T.ay = mi.ay;

@@ -57,6 +57,8 @@ struct KArgs {
     const void* lay;   // layer table of the chains' precision
     const double* lay64; // FP64 layer table
     int32_t L_total, n_edges;
+    int32_t layered; // some medium has more than one layer
+    int32_t has_sl;  // some layer has a Rayleigh-like fraction f_SL > 0
     size_t tab_bytes; // LDS bytes of the staged tables (0: read them from HBM)
     // run
     uint64_t seed, step0;

@@ -1,0 +1,724 @@
+// rj_step.h -- the fused reversible-jump step kernel for gfx950 (templates;
+// instantiated per precision and sampler in the rj_run_*.hip units).
+//
+// One chain per lane.  A block owns a tile of chains for every step of the
+// launch.  The first V vertices of each chain live in LDS in a vertex-major,
+// lane-minor layout ([slot][lane]: per-lane random slots stay conflict-free),
+// the rest stay in the caller's HBM array (same [v][C] layout, read and
+// written coalesced at launch start and end).  When every lane of a wave fits
+// its LDS slots (a wave vote per step) the step runs a branch-free LDS-only
+// instantiation.  Layered media are staged in LDS once per block; a
+// homogeneous medium lives in registers.
+//
+// Every step of a launch is the same move class for all lanes (the move
+// schedule depends only on the global step index), so waves diverge only
+// inside a class: interior and end-point perturbations share one
+// local-density evaluator, births and deaths share one jump evaluator.
+//
+// Method references: path density (App. "Path probability distribution"),
+// jump proposal and bi-spherical map (App. "Jump proposal", "Dimension
+// matching transformation"), acceptance (eq. acceptFact read in Green's
+// form), end-point move on the sensor and proposal mix (Sec. "Path proposal
+// distribution"); the Langevin move follows the Discussion's suggestion of
+// gradient-informed moves.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "rj_device.h"
+#include "rj_kernels.h"
+
+namespace rj {
+
+enum { MV_INTERIOR = 0, MV_END = 1, MV_BIRTH = 2, MV_DEATH = 3, MV_MALA = 4, MV_NULL = 5 };
+
+// Lane-private path storage: slots below V in LDS, the rest in HBM.  LO: the
+// whole path is known to be in LDS.  The LDS side is addressed through an
+// address-space-3 pointer to a 4-vector, so that every access is one ds_*
+// instruction (never a generic flat access).
+template <class R> using L4 = R __attribute__((ext_vector_type(4)));
+template <class R> using LdsPtr = __attribute__((address_space(3))) L4<R>*;
+template <class R> using LdsScalar = __attribute__((address_space(3))) R*;
+
+template <class R> __device__ __forceinline__ Vtx<R> lds_ld(LdsPtr<R> p) {
+    const L4<R> q = *p;
+    return Vtx<R>{q.x, q.y, q.z, q.w};
+}
+template <class R> __device__ __forceinline__ void lds_st(LdsPtr<R> p, const Vtx<R>& x) { *p = L4<R>{x.x, x.y, x.z, x.w}; }
+
+template <class R, bool LO> struct PathRef {
+    LdsPtr<R> lds; // this lane's slot 0, stride bs
+    Vtx<R>* glb;   // this chain's vertex 0, stride C
+    int bs, V;
+    size_t C;
+    __device__ __forceinline__ Vtx<R> ld(int v) const {
+        if (LO || v < V) return lds_ld<R>(lds + v * bs);
+        return glb[(size_t)v * C];
+    }
+    __device__ __forceinline__ void st(int v, const Vtx<R>& x) const {
+        if (LO || v < V) lds_st<R>(lds + v * bs, x);
+        else glb[(size_t)v * C] = x;
+    }
+    __device__ __forceinline__ V3<R> p(int v) const { return pos(ld(v)); }
+    __device__ __forceinline__ R w(int v) const {
+        if (LO || v < V) return ((LdsScalar<R>)(lds + v * bs))[3];
+        return glb[(size_t)v * C].w;
+    }
+    __device__ __forceinline__ void stw(int v, R x) const {
+        if (LO || v < V) ((LdsScalar<R>)(lds + v * bs))[3] = x;
+        else glb[(size_t)v * C].w = x;
+    }
+};
+
+template <class R> struct GlobalPath {
+    Vtx<R>* glb;
+    size_t C;
+    __device__ __forceinline__ Vtx<R> ld(int v) const { return glb[(size_t)v * C]; }
+    __device__ __forceinline__ V3<R> p(int v) const { return pos(ld(v)); }
+    __device__ __forceinline__ void stw(int, R) const {}
+};
+
+// Full log p of the path (FP64 sum of the factors), refreshing the cached
+// segment scattering depths; also returns the path length L.
+template <class R, class P>
+__device__ __forceinline__ double full_logp(const Tgt<R>& T, const P& ps, int n, double& L) {
+    V3<R> f0 = ps.p(0), f1 = ps.p(1);
+    Seg<R> s = make_seg(T, f0, f1);
+    bool zero = !(s.len > (R)0);
+    double lp = (double)emit_term(T, s.u) + (double)seg_term(s);
+    L = (double)s.len;
+    ps.stw(0, s.tb);
+    V3<R> fc = f1;
+    for (int k = 1; k <= n - 2; ++k) {
+        V3<R> fn = ps.p(k + 1);
+        Seg<R> s2 = make_seg(T, fc, fn);
+        zero |= !(s2.len > (R)0);
+        const LayV<R> ly = lay_of(T, fc);
+        lp += (double)(ly.logb + turn_term(ly, s.u, s2.u)) + (double)seg_term(s2);
+        L += (double)s2.len;
+        ps.stw(k, s2.tb);
+        s = s2;
+        fc = fn;
+    }
+    lp += (double)end_term(T, s.u, fc);
+    if (zero) lp = -__builtin_inf();
+    return lp;
+}
+
+// q(s) of the bi-spherical proposal with concentration beta, in the two
+// forms the jump needs: E = e^{-2 beta}, the normaliser
+// log((1 - E) / beta) = log(2 sinh(beta) / beta) - beta, and the inverse CDF
+// of cos s written as w = 1 + cos s = -log(u' + (1 - u') E) / beta with
+// u' = 1 - u.  For beta >= 1/4 the direct forms lose nothing (1 - E > 0.39);
+// below that the expm1 / log1p forms are used.
+template <class R> struct QS {
+    R beta, E, ibeta, lnorm;
+    bool small;
+};
+
+template <class R> __device__ __forceinline__ QS<R> make_qs(R beta) {
+    QS<R> q;
+    q.beta = beta;
+    R ab = beta < (R)0 ? -beta : beta;
+    q.small = ab < (R)0.25;
+    q.E = Mth<R>::exp((R)-2 * beta);
+    q.ibeta = Mth<R>::rcp(beta);
+    if (!q.small) {
+        q.lnorm = Mth<R>::log(((R)1 - q.E) * q.ibeta);
+    } else if (ab < (R)1e-6) {
+        q.lnorm = (R)0.69314718055994530942 - beta;
+    } else {
+        q.lnorm = Mth<R>::log(-Mth<R>::expm1((R)-2 * beta) * q.ibeta);
+    }
+    return q;
+}
+
+// 1 + cos s from the uniform u (inverse CDF of q(s))
+template <class R> __device__ __forceinline__ R qs_sample(const QS<R>& q, R u) {
+    R up = (R)1 - u;
+    if (!q.small) return -Mth<R>::log(u + up * q.E) * q.ibeta;
+    R ab = q.beta < (R)0 ? -q.beta : q.beta;
+    if (ab < (R)1e-6) return (R)2 * up;
+    return -Mth<R>::log1p(up * Mth<R>::expm1((R)-2 * q.beta)) * q.ibeta;
+}
+
+template <class R>
+__device__ __forceinline__ void box_muller3(uint32_t a, uint32_t b, uint32_t c, uint32_t d, V3<R>& xi) {
+    R u0 = unif<R>(a), u1 = unif<R>(b), u2 = unif<R>(c), u3 = unif<R>(d);
+    R rho1 = Mth<R>::sqrt((R)-2 * Mth<R>::log(u0));
+    R rho2 = Mth<R>::sqrt((R)-2 * Mth<R>::log(u2));
+    xi = {rho1 * Mth<R>::cos2pi(u1), rho1 * Mth<R>::sin2pi(u1), rho2 * Mth<R>::cos2pi(u3)};
+}
+
+// ---------------------------------------------------------------------------
+// Score of the path: log p and d log p / d vertex, streamed along the path
+// with a three-vertex register window.  emit(k, g) receives the finished
+// gradient of vertex k (k = 0 .. n-1, in increasing order).
+// ---------------------------------------------------------------------------
+template <class R>
+__device__ __forceinline__ void seg_depth_grad(const Tgt<R>& T, V3<R> P, V3<R> Q, const Seg<R>& s, V3<R>& dP,
+                                               V3<R>& dQ) {
+    R F = s.tc / s.len; // mean total coefficient along the segment
+    dP = (-F) * s.u;
+    dQ = F * s.u;
+    if (T.mcnt > 1) {
+        double uP = axis_u(T, P), uQ = axis_u(T, Q);
+        int lP = layer_u(T, uP), lQ = layer_u(T, uQ);
+        if (lP != lQ) {
+            double cP = (double)T.lay[lP * LY_NW + LY_C], cQ = (double)T.lay[lQ * LY_NW + LY_C];
+            double inv = 1.0 / (uQ - uP);
+            R gP = (R)((double)s.len * ((double)F - cP) * inv);
+            R gQ = (R)((double)s.len * (cQ - (double)F) * inv);
+            V3<R> ax = {(R)T.ax, (R)T.ay, (R)T.az};
+            dP = dP + gP * ax;
+            dQ = dQ + gQ * ax;
+        }
+    }
+}
+
+// d log sigma / d mu at a turn, q = |ua - ub|^2
+template <class R> __device__ __forceinline__ R dturn_dmu(const LayV<R>& ly, R q) {
+    R den = ly.hg1 + ly.g * q;
+    R dhg = (R)3 * ly.g / den;
+    if (ly.fsl == (R)0) return dhg;
+    R hg = ly.hgn - (R)1.5 * Mth<R>::log(den);
+    R v = (R)1 - (R)0.25 * q; // (1 + mu) / 2
+    R sl = ly.sln + ly.sla * Mth<R>::log(v);
+    R dsl = ly.sla / ((R)2 * v);
+    R m = sl > hg ? sl : hg;
+    R es = ly.fsl * Mth<R>::exp(sl - m), eh = ((R)1 - ly.fsl) * Mth<R>::exp(hg - m);
+    return (es * dsl + eh * dhg) / (es + eh);
+}
+
+template <class R> __device__ __forceinline__ V3<R> dunit(V3<R> u, R len, V3<R> c) {
+    // d (u . c) / d r for u = r / |r|
+    R il = (R)1 / len;
+    return il * (c - dot(u, c) * u);
+}
+
+template <class R, class P, class Emit>
+__device__ __forceinline__ double score_stream(const Tgt<R>& T, const P& ps, int n, Emit emit) {
+    V3<R> z = {(R)0, (R)0, (R)0};
+    V3<R> gA = z, gB = z, gC = z; // vertices k-2, k-1, k
+    V3<R> fprev = ps.p(0), fcur;
+    Seg<R> sprev;
+    double lp = 0.0;
+    bool zero = false;
+    for (int k = 1; k < n; ++k) {
+        fcur = ps.p(k);
+        Seg<R> s = make_seg(T, fprev, fcur);
+        zero |= !(s.len > (R)0);
+        lp += (double)seg_term(s);
+        V3<R> dP, dQ;
+        seg_depth_grad(T, fprev, fcur, s, dP, dQ);
+        R il2 = (R)2 / s.len;
+        gB = gB - dP + il2 * s.u;
+        gC = gC - dQ - il2 * s.u;
+        if (k == 1) {
+            lp += (double)emit_term(T, s.u);
+            if (T.ek == RJPATH_EMIT_VMF) {
+                V3<R> d = T.kappa * dunit(s.u, s.len, T.ed);
+                gC = gC + d;
+                gB = gB - d;
+            }
+        } else {
+            // turn (and scattering density) at vertex k-1 between sprev and s
+            const LayV<R> ly = lay_of(T, fprev);
+            V3<R> dd = sprev.u - s.u;
+            lp += (double)(ly.logb + turn_term(ly, sprev.u, s.u));
+            R h = dturn_dmu(ly, dot(dd, dd));
+            V3<R> da = dunit(sprev.u, sprev.len, s.u);
+            V3<R> db = dunit(s.u, s.len, sprev.u);
+            gA = gA - h * da;
+            gB = gB + h * da - h * db;
+            gC = gC + h * db;
+            emit(k - 2, gA);
+        }
+        gA = gB;
+        gB = gC;
+        gC = z;
+        sprev = s;
+        fprev = fcur;
+    }
+    // end term on segment n-2 and the end point (gA = vertex n-2, gB = vertex n-1)
+    lp += (double)end_term(T, sprev.u, fprev);
+    V3<R> d = fprev - T.eta;
+    R dn2 = dot(d, d);
+    R idn = Mth<R>::rsqrt(dn2);
+    V3<R> nu = idn * d;
+    R c = -dot(sprev.u, nu);
+    R ic = (R)1 / c;
+    V3<R> dcr = (R)-1 * dunit(sprev.u, sprev.len, nu);
+    V3<R> dcd = (R)-1 * dunit(nu, dn2 * idn, sprev.u);
+    gA = gA - ic * dcr;
+    gB = gB + ic * dcr + ic * dcd;
+    if (T.dk == RJPATH_DET_PAPER) {
+        R cr = dot(nu, T.dd);
+        R th = tanh((R)2 * cr + (R)0.7);
+        gB = gB + ((R)3 - (R)2 * th) * dunit(nu, dn2 * idn, T.dd);
+    }
+    if (n >= 3) emit(n - 2, gA);
+    emit(n - 1, gB);
+    if (zero) lp = -__builtin_inf();
+    return lp;
+}
+
+// ---------------------------------------------------------------------------
+// One factor of the path density attached to one vertex (App. "Path
+// probability distribution"), evaluated branch-free so that lanes of a wave
+// whose vertices play different roles do not diverge:
+//   VK_EMIT: the source, log eps(ub) of the first direction;
+//   VK_TURN: an interior vertex, log b + log sigma_sr(ua . ub);
+//   VK_END:  the end point fe, log max(0, -ua . nu) + log rho(nu);
+//   VK_NONE: no vertex (0).
+// CE / CT / CN: whether the kinds END / EMIT / NONE can occur at the call.
+// ---------------------------------------------------------------------------
+enum { VK_EMIT = 0, VK_TURN = 1, VK_END = 2, VK_NONE = 3 };
+
+template <class R> __device__ __forceinline__ R rho_log(const Tgt<R>& T, V3<R> nu) {
+    if (T.dk != RJPATH_DET_PAPER) return (R)0;
+    R cr = dot(nu, T.dd);
+    R z = (R)2 * cr + (R)0.7;
+    R az = z < (R)0 ? -z : z;
+    // log rho = 3 c - 1 - log cosh(2 c + 0.7), log cosh z = |z| + log1p(e^{-2|z|}) - log 2
+    return (R)3 * cr - (R)1 - (az + Mth<R>::log1p(Mth<R>::exp((R)-2 * az)) - (R)0.69314718055994530942);
+}
+
+template <class R, bool CE, bool CT, bool CN>
+__device__ __forceinline__ R vtx_term(const Tgt<R>& T, int kind, const LayV<R>& ly, V3<R> ua, V3<R> ub, V3<R> fe) {
+    V3<R> d = ua - ub;
+    R X = ly.hg1 + ly.g * dot(d, d); // HG denominator, 1 - mu = |ua - ub|^2 / 2
+    V3<R> nu = {(R)0, (R)0, (R)0};
+    R ce = (R)1;
+    if (CE) {
+        V3<R> de = fe - T.eta;
+        nu = Mth<R>::rsqrt(dot(de, de)) * de;
+        ce = -dot(ua, nu);
+        if (kind == VK_END) X = ce;
+    }
+    const R lx = Mth<R>::log(X);
+    R turn = ly.logb + ly.hgn - (R)1.5 * lx;
+    if (ly.fsl != (R)0) {
+        R q = dot(d, d);
+        R hg = ly.hgn - (R)1.5 * lx;
+        R sl = ly.sln + ly.sla * Mth<R>::log((R)1 - (R)0.25 * q);
+        R m = sl > hg ? sl : hg;
+        turn = ly.logb + m + Mth<R>::log(ly.fsl * Mth<R>::exp(sl - m) + ((R)1 - ly.fsl) * Mth<R>::exp(hg - m));
+    }
+    R out = turn;
+    if (CE && kind == VK_END) out = ce > (R)0 ? lx + rho_log(T, nu) : Mth<R>::ninf();
+    if (CT && kind == VK_EMIT) out = emit_term(T, ub);
+    if (CN && kind == VK_NONE) out = (R)0;
+    return out;
+}
+
+// ---------------------------------------------------------------------------
+// Per-lane sampler state and statistics.
+// ---------------------------------------------------------------------------
+template <class R> struct Lane {
+    int n;
+    double L;    // path length (running sum; refreshed at launch start)
+    double lp;   // log p (refreshed at launch start and end)
+    double invw; // 1 / w(n)
+    // statistics of this launch
+    double a1, a2, sl, sl2;
+    uint32_t cnt, c2, sn, ncap, pp, pb, pd, ap, ab, ad, mp, ma;
+};
+
+struct StepCtx {
+    uint32_t chain, k0, k1;
+    int cap;
+    uint32_t bthresh;
+    float log_pb, log_pd;
+    double sigma, ikappa, e2k, mala_h;
+    int sampler;
+    const double* logw;
+};
+
+// One step of one lane; returns the move kind, writes log A / accepted / index.
+template <class R, bool LO, bool MALA>
+__device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>& ps, const GlobalPath<R>& work,
+                                          Lane<R>& ln, const StepCtx& sc, uint64_t step, bool perturb, int& move,
+                                          int& idx, int& accepted, R& logA, R& logu) {
+    uint32_t r[8];
+    {
+        uint32_t q0[4] = {sc.chain, (uint32_t)step, (uint32_t)(step >> 32), 0u};
+        uint32_t q1[4] = {sc.chain, (uint32_t)step, (uint32_t)(step >> 32), 1u};
+        philox4x32_10(q0, sc.k0, sc.k1);
+        philox4x32_10(q1, sc.k0, sc.k1);
+        r[0] = q0[0]; r[1] = q0[1]; r[2] = q0[2]; r[3] = q0[3];
+        r[4] = q1[0]; r[5] = q1[1]; r[6] = q1[2]; r[7] = q1[3];
+    }
+    const int n = ln.n;
+    logu = Mth<R>::log(unif<R>(r[1]));
+    move = MV_NULL;
+    idx = -1;
+    accepted = 0;
+    logA = Mth<R>::ninf();
+    const V3<R> ex = {(R)1, (R)0, (R)0};
+    if (perturb) {
+        const int j = 1 + pick(r[0], (uint32_t)(n - 1));
+        idx = j;
+        const bool is_end = (j == n - 1);
+        if (MALA && !is_end) {
+            // ---------- joint Langevin move of all interior vertices ----------
+            move = MV_MALA;
+            const R h = (R)sc.mala_h, hh = (R)0.5 * h, sh = Mth<R>::sqrt(h);
+            double half_xi2 = 0.0;
+            double lpx = score_stream(T, ps, n, [&](int k, V3<R> g) {
+                Vtx<R> x = ps.ld(k);
+                V3<R> y = pos(x);
+                if (k >= 1 && k <= n - 2) {
+                    uint32_t q[4] = {sc.chain, (uint32_t)step, (uint32_t)(step >> 32), 2u + (uint32_t)k};
+                    philox4x32_10(q, sc.k0, sc.k1);
+                    V3<R> xi;
+                    box_muller3<R>(q[0], q[1], q[2], q[3], xi);
+                    half_xi2 += 0.5 * (double)dot(xi, xi);
+                    y = y + hh * g + sh * xi;
+                }
+                work.glb[(size_t)k * work.C] = Vtx<R>{y.x, y.y, y.z, (R)0};
+            });
+            double rev = 0.0;
+            double lpy = score_stream(T, work, n, [&](int k, V3<R> g) {
+                if (k >= 1 && k <= n - 2) {
+                    V3<R> d = ps.p(k) - work.p(k) - hh * g;
+                    rev += (double)dot(d, d) / (2.0 * (double)h);
+                }
+            });
+            double la = lpy - lpx - rev + half_xi2;
+            logA = isfinite(lpy) ? (R)la : Mth<R>::ninf();
+            if (logu < logA) {
+                accepted = 1;
+                for (int k = 1; k <= n - 2; ++k) ps.st(k, work.ld(k));
+                full_logp(T, ps, n, ln.L); // refresh the cached depths and L
+            }
+            return;
+        }
+        // ---------- single-vertex perturbation: the five-vertex window ----------
+        const bool hm2 = j >= 2, hp1 = !is_end, hp2 = j <= n - 3;
+        const V3<R> fm1 = ps.p(j - 1), fo = ps.p(j);
+        // absent neighbours are replaced by harmless stand-ins (loads stay in range)
+        const V3<R> gm2 = ps.p(hm2 ? j - 2 : 0), gp1 = ps.p(hp1 ? j + 1 : 0), gp2 = ps.p(hp2 ? j + 2 : 0);
+        const V3<R> fm2 = hm2 ? gm2 : fm1 - ex;
+        const V3<R> fp1 = hp1 ? gp1 : fo + ex;
+        const V3<R> fp2 = hp2 ? gp2 : fp1 + ex;
+        move = is_end ? MV_END : MV_INTERIOR;
+        // one log and one sin/cos pair serve both proposals: Box-Muller on
+        // words 4..7 for the Gaussian step, and words 4, 5 for the end-point
+        // von Mises-Fisher step (inverse CDF of its cosine, uniform azimuth)
+        const R u4 = unif<R>(r[4]), u5 = unif<R>(r[5]);
+        const R lg = Mth<R>::log(is_end ? u4 + ((R)1 - u4) * (R)sc.e2k : u4);
+        const R c5 = Mth<R>::cos2pi(u5), s5 = Mth<R>::sin2pi(u5);
+        V3<R> fn;
+        {
+            const R rho1 = Mth<R>::sqrt((R)-2 * lg);
+            const R rho2 = Mth<R>::sqrt((R)-2 * Mth<R>::log(unif<R>(r[6])));
+            const V3<R> xi = {rho1 * c5, rho1 * s5, rho2 * Mth<R>::cos2pi(unif<R>(r[7]))};
+            const V3<R> fg = fo + (R)sc.sigma * xi;
+            V3<R> dd = fo - T.eta;
+            V3<R> nu = Mth<R>::rsqrt(dot(dd, dd)) * dd, e2, e3;
+            onb(nu, e2, e3);
+            const R omw = -lg * (R)sc.ikappa; // 1 - cos
+            const R wv = (R)1 - omw;
+            const R sw = Mth<R>::sqrt(fmax(omw * ((R)2 - omw), (R)0));
+            const V3<R> fv = T.eta + T.rad * (wv * nu + sw * (c5 * e2 + s5 * e3));
+            fn = is_end ? fv : fg;
+        }
+        const Seg<R> Ao = make_seg(T, fm1, fo), An = make_seg(T, fm1, fn);
+        const Seg<R> Bo = make_seg(T, fo, fp1), Bn = make_seg(T, fn, fp1);
+        const V3<R> um = unit_dir(fm2, fm1), up = unit_dir(fp1, fp2);
+        const LayV<R> lm1 = lay_of(T, fm1), lo = lay_of(T, fo), lnw = lay_of(T, fn), lp1 = lay_of(T, fp1);
+        const int km1 = hm2 ? VK_TURN : VK_EMIT;
+        const int kj = is_end ? VK_END : VK_TURN;
+        const int kp1 = !hp1 ? VK_NONE : (hp2 ? VK_TURN : VK_END);
+        R d = seg_term(An) - seg_term(Ao);
+        d += hp1 ? seg_term(Bn) - seg_term(Bo) : (R)0;
+        d += vtx_term<R, false, true, false>(T, km1, lm1, um, An.u, fm1) -
+             vtx_term<R, false, true, false>(T, km1, lm1, um, Ao.u, fm1);
+        d += vtx_term<R, true, false, false>(T, kj, lnw, An.u, Bn.u, fn) -
+             vtx_term<R, true, false, false>(T, kj, lo, Ao.u, Bo.u, fo);
+        d += vtx_term<R, true, false, true>(T, kp1, lp1, Bn.u, up, fp1) -
+             vtx_term<R, true, false, true>(T, kp1, lp1, Bo.u, up, fp1);
+        logA = d;
+        if (logu < logA) {
+            accepted = 1;
+            ps.st(j, Vtx<R>{fn.x, fn.y, fn.z, hp1 ? Bn.tb : (R)0});
+            ps.stw(j - 1, An.tb);
+            ln.L += (double)An.len - (double)Ao.len + (hp1 ? (double)Bn.len - (double)Bo.len : 0.0);
+        }
+        return;
+    }
+    // ---------- birth / death through the bi-spherical map ----------
+    const bool birth = r[2] < sc.bthresh;
+    move = birth ? MV_BIRTH : MV_DEATH;
+    // the tilt values the move can need, fetched early so that their latency
+    // hides behind the proposal arithmetic
+    double lwm = 0.0, lw0 = 0.0, lwp = 0.0;
+    if (sc.logw) {
+        lwm = sc.logw[n - 1];
+        lw0 = sc.logw[n];
+        lwp = sc.logw[n < sc.cap ? n + 1 : n];
+    }
+    // S = sum of the cached segment depths, summed afresh in a fixed order (so
+    // the chain does not depend on where launches start and end).  The first
+    // WB depths are read once into registers (loads issued together) and
+    // serve both the sum and the segment scan.
+    constexpr int WB = 8;
+    R wv[WB];
+#pragma unroll
+    for (int v = 0; v < WB; ++v) wv[v] = ps.w(v < n - 1 ? v : 0);
+    double S = 0.0;
+#pragma unroll
+    for (int v = 0; v < WB; ++v) S += v < n - 1 ? (double)wv[v] : 0.0;
+    for (int v = WB; v < n - 1; ++v) S += (double)ps.w(v);
+    const bool valid = birth ? (n < sc.cap && S > 0.0) : (n > 2);
+    int iA = 0, jv = 1;
+    if (valid) {
+        if (birth) {
+            // segment k with probability tau_b(k) / S: the first k whose
+            // cumulative depth exceeds U S, i.e. the number of prefixes that
+            // do not (the cumulative sums never decrease)
+            const double tgt = (double)unif<double>(r[0]) * S;
+            double cum = 0.0;
+            int k = 0;
+#pragma unroll
+            for (int v = 0; v < WB; ++v) {
+                cum += v < n - 1 ? (double)wv[v] : 0.0;
+                k += (v < n - 1 && cum <= tgt) ? 1 : 0;
+            }
+            for (int v = WB; v < n - 1; ++v) {
+                cum += (double)ps.w(v);
+                k += cum <= tgt ? 1 : 0;
+            }
+            k = k < n - 2 ? k : n - 2;
+            iA = k;
+        } else {
+            jv = 1 + pick(r[0], (uint32_t)(n - 2));
+            iA = jv - 1;
+        }
+        idx = birth ? iA : jv;
+    }
+    const int iB = birth ? iA + 1 : iA + 2;
+    const bool hprev = iA >= 1, hnext = iB + 1 <= n - 1;
+    const V3<R> A = ps.p(iA), B = ps.p(iB < n ? iB : n - 1);
+    const V3<R> gprev = ps.p(hprev ? iA - 1 : 0), gnext = ps.p(hnext ? iB + 1 : 0);
+    const V3<R> fprev = hprev ? gprev : A - ex;
+    const V3<R> fnext = hnext ? gnext : B + ex;
+    const V3<R> fj = ps.p(jv);
+    const Seg<R> AB = make_seg(T, A, B);
+    const V3<R> mid = (R)0.5 * (A + B);
+    const LayV<R> lm = lay_of(T, mid);
+    const R gam = (R)0.5 * AB.len;
+    const R beta = lm.keq + (R)0.5 * (gam * lm.b - (R)1); // centering rule at the midpoint
+    const QS<R> qs = make_qs(beta);
+    V3<R> fv;
+    {
+        // the bi-spherical proposal (used by births; deaths take the vertex itself)
+        R w = qs_sample(qs, unif<R>(r[4])); // 1 + cos s by the inverse CDF of q(s)
+        // t from the logistic q(t): e^t = a/(1-a); sinh t and cosh t - cos s in closed form
+        R a5 = unif<R>(r[5]), b5 = (R)1 - a5, ab2 = (R)2 * a5 * b5;
+        R ss = Mth<R>::sqrt(fmax(w * ((R)2 - w), (R)0));
+        R ph = unif<R>(r[6]);
+        V3<R> e2, e3;
+        onb(AB.u, e2, e3);
+        R sc_ = gam * Mth<R>::rcp((R)1 - ab2 * w);
+        V3<R> tr = Mth<R>::cos2pi(ph) * e2 + Mth<R>::sin2pi(ph) * e3;
+        const V3<R> fb = mid + sc_ * ((a5 - b5) * AB.u + (ab2 * ss) * tr);
+        fv = birth ? fb : fj;
+    }
+    const Seg<R> sA = make_seg(T, A, fv), sB = make_seg(T, fv, B);
+    const V3<R> up = unit_dir(fprev, A), un = unit_dir(B, fnext);
+    const LayV<R> la = lay_of(T, A), lb = lay_of(T, B), lv = lay_of(T, fv);
+    const int kA = hprev ? VK_TURN : VK_EMIT, kB = hnext ? VK_TURN : VK_END;
+    const R tx = vtx_term<R, false, true, false>(T, kA, la, up, AB.u, A) +
+                 vtx_term<R, true, false, false>(T, kB, lb, AB.u, un, B);
+    const R ty = vtx_term<R, false, true, false>(T, kA, la, up, sA.u, A) +
+                 vtx_term<R, true, false, false>(T, kB, lb, sB.u, un, B) +
+                 vtx_term<R, false, false, false>(T, VK_TURN, lv, sA.u, sB.u, fv);
+    V3<R> dq = sA.u - sB.u;
+    R q = dot(dq, dq);
+    // segment factors of y over x times |J| / q(s) q(t) q(phi): the inverse-square
+    // factors of the two new segments cancel against J; 1 + cos s = q / 2
+    const R LOG2PI = (R)1.83787706640934548356;
+    R jac = -sA.tc - sB.tc + AB.tc + (R)2 * Mth<R>::log(sA.len + sB.len) - AB.loglen + qs.lnorm +
+            (R)0.5 * beta * q + LOG2PI;
+    const int nx = birth ? n : n - 1;
+    const double Sx = birth ? S : S - (double)ps.w(iA) - (double)ps.w(jv) + (double)AB.tb;
+    R lpup = (R)sc.log_pb + Mth<R>::log(AB.tb) - Mth<R>::log((R)Sx);
+    R lpdn = (R)sc.log_pd - Mth<R>::log((R)(nx - 1));
+    R dlw = (sc.logw && valid) ? (R)(birth ? lwp - lw0 : lw0 - lwm) : (R)0; // logw[nx + 1] - logw[nx]
+    R logAb = (ty - tx) + jac + dlw + lpdn - lpup;
+    logA = valid ? (birth ? logAb : -logAb) : Mth<R>::ninf();
+    if (logu < logA) {
+        accepted = 1;
+        const double dL = (double)sA.len + (double)sB.len - (double)AB.len;
+        if (birth) {
+            for (int v = n - 1; v >= iB; --v) ps.st(v + 1, ps.ld(v));
+            ps.st(iB, Vtx<R>{fv.x, fv.y, fv.z, sB.tb});
+            ps.stw(iA, sA.tb);
+            ln.L += dL;
+            ln.n = n + 1;
+        } else {
+            for (int v = jv; v <= n - 2; ++v) ps.st(v, ps.ld(v + 1));
+            ps.stw(iA, AB.tb);
+            ln.L -= dL;
+            ln.n = n - 1;
+        }
+        ln.invw = sc.logw ? exp(-(birth ? lwp : lwm)) : 1.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The step kernel.  MK: MK_HOM (every medium of the launch is homogeneous: the
+// layer lookups fold away), MK_LAY (layer tables read from HBM) or MK_LAY_LDS
+// (tables staged in LDS).  SL: some layer mixes in the Rayleigh-like term.
+// ---------------------------------------------------------------------------
+enum { MK_HOM = 0, MK_LAY = 1, MK_LAY_LDS = 2 };
+
+template <class R, int MK, bool MALA, bool SL>
+__global__ void __launch_bounds__(256) run_kernel(KArgs a) {
+    constexpr bool TAB = MK == MK_LAY_LDS;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int tid = threadIdx.x, bs = blockDim.x;
+    MedTab<R> tab = hbm_tab<R>(a);
+    size_t tab_bytes = 0;
+    if (TAB) {
+        // layer table, then edges, then prefix integrals, each 16-byte aligned
+        const size_t nl = (size_t)a.L_total * LY_NW, ne = (size_t)a.n_edges;
+        R* lay = (R*)smem;
+        double* edge = (double*)(smem + ((nl * sizeof(R) + 15) & ~(size_t)15));
+        double* pre = edge + ((ne + 1) & ~(size_t)1);
+        for (size_t i = tid; i < nl; i += bs) lay[i] = ((const R*)a.lay)[i];
+        for (size_t i = tid; i < ne; i += bs) edge[i] = a.edge[i];
+        for (size_t i = tid; i < 2 * ne; i += bs) pre[i] = a.pre[i];
+        __syncthreads();
+        tab = MedTab<R>{lay, edge, pre};
+        tab_bytes = a.tab_bytes;
+    }
+    const int c = blockIdx.x * bs + tid;
+    if (c >= a.C) return;
+    const size_t C = (size_t)a.C;
+    LdsPtr<R> lslots = (LdsPtr<R>)((L4<R>*)(smem + tab_bytes) + tid);
+    const int t = a.target[c];
+    Lane<R> ln{};
+    ln.n = a.n[c];
+    const int cap = a.cap;
+    // malformed chains are flagged and never touched
+    if (t < 0 || t >= a.T || ln.n < 2 || ln.n > cap || a.medium[t] < 0 || a.medium[t] >= a.n_media) {
+        a.status[c] = 1;
+        return;
+    }
+    Tgt<R> T;
+    load_target(a, t, T, tab);
+    // compile-time facts of this instantiation (the lookups that test them fold)
+    if (MK == MK_HOM) T.mcnt = 1;
+    T.sl = SL;
+    if (!SL) T.l0.fsl = (R)0;
+    PathRef<R, false> ps{lslots, (Vtx<R>*)a.verts + c, bs, a.V, C};
+    PathRef<R, true> pl{lslots, (Vtx<R>*)a.verts + c, bs, a.V, C};
+    GlobalPath<R> work{a.work ? (Vtx<R>*)a.work + c : nullptr, C};
+    // stage the LDS part of the path
+    const int nl0 = ln.n < a.V ? ln.n : a.V;
+    for (int v = 0; v < nl0; ++v) lds_st<R>(ps.lds + v * bs, ps.glb[(size_t)v * C]);
+
+    ln.lp = full_logp(T, ps, ln.n, ln.L);
+    const bool healthy = isfinite(ln.lp);
+    a.status[c] = healthy ? 0 : 1;
+
+    StepCtx sc;
+    sc.chain = (uint32_t)c;
+    sc.k0 = (uint32_t)a.seed;
+    sc.k1 = (uint32_t)(a.seed >> 32);
+    sc.cap = cap;
+    sc.bthresh = a.bthresh;
+    const double pb = (double)a.bthresh * 0x1p-32;
+    sc.log_pb = (float)log(pb);
+    sc.log_pd = (float)log1p(-pb);
+    sc.sigma = a.sigma;
+    sc.ikappa = 1.0 / a.kappa_end;
+    sc.e2k = exp(-2.0 * a.kappa_end);
+    sc.mala_h = a.mala_h;
+    sc.sampler = a.sampler;
+    sc.logw = a.logw ? a.logw + (size_t)t * (cap + 1) : nullptr;
+    ln.invw = sc.logw ? exp(-sc.logw[ln.n]) : 1.0;
+    const uint64_t step0 = a.step_dev ? *a.step_dev + a.step0 : a.step0; // step0 is the offset then
+    int phase = (int)(step0 % (uint64_t)a.cycle_len);
+
+    for (int s = 0; s < a.steps && healthy; ++s) {
+        const uint64_t step = step0 + (uint64_t)s;
+        const bool perturb = phase < a.n_perturb;
+        int move, idx, accepted;
+        R logA, logu;
+        // the LDS-only instantiation when every active lane's path (and a birth) fits its slots
+        if (__all(ln.n < a.V))
+            step_body<R, true, MALA>(T, pl, work, ln, sc, step, perturb, move, idx, accepted, logA, logu);
+        else
+            step_body<R, false, MALA>(T, ps, work, ln, sc, step, perturb, move, idx, accepted, logA, logu);
+        if ((int64_t)step >= a.burn_in) {
+            const int n = ln.n;
+            ln.cnt += 1;
+            ln.c2 += (n == T.n0);
+            if (sc.logw) {
+                ln.a1 += ln.invw;
+                if (n == T.n0) ln.a2 += ln.invw;
+            }
+            ln.sl += ln.L;
+            ln.sl2 += ln.L * ln.L;
+            ln.sn += n;
+            ln.ncap += (n == cap);
+            if (move == MV_BIRTH) {
+                ln.pb += 1;
+                ln.ab += accepted;
+            } else if (move == MV_DEATH) {
+                ln.pd += 1;
+                ln.ad += accepted;
+            } else {
+                ln.pp += 1;
+                ln.ap += accepted;
+            }
+            if (move == MV_MALA) {
+                ln.mp += 1;
+                ln.ma += accepted;
+            }
+            if (a.hist) atomicAdd(a.hist + (size_t)t * (cap + 1) + n, 1u);
+        }
+        if (a.trace) {
+            double* tr = a.trace + ((size_t)c * a.trace_steps + a.trace_off + s) * RJPATH_TRACE_WORDS;
+            tr[0] = move;
+            tr[1] = accepted;
+            tr[2] = idx;
+            tr[3] = (double)logA;
+            tr[4] = (double)logu;
+        }
+        phase = (phase + 1 == a.cycle_len) ? 0 : phase + 1;
+    }
+
+    // log p of the final path (refreshed once rather than tracked per step)
+    if (healthy) ln.lp = full_logp(T, ps, ln.n, ln.L);
+    // write back the LDS part, the vertex count, log p and the statistics
+    const int nw = ln.n < a.V ? ln.n : a.V;
+    for (int v = 0; v < nw; ++v) ps.glb[(size_t)v * C] = lds_ld<R>(ps.lds + v * bs);
+    a.n[c] = ln.n;
+    a.logp[c] = ln.lp;
+    if (healthy) {
+        double* sp = a.stats + (size_t)c * RJPATH_NSTAT;
+        sp[0] += ln.cnt;
+        // without a sector tilt 1/w = 1 and the two sums are counts
+        sp[1] += sc.logw ? ln.a1 : (double)ln.cnt;
+        sp[2] += sc.logw ? ln.a2 : (double)ln.c2;
+        sp[3] += ln.sl;
+        sp[4] += ln.sl2;
+        sp[5] += ln.sn;
+        sp[6] += ln.pp;
+        sp[7] += ln.pb;
+        sp[8] += ln.pd;
+        sp[9] += ln.ap;
+        sp[10] += ln.ab;
+        sp[11] += ln.ad;
+        sp[12] += ln.ncap;
+        sp[13] += ln.mp;
+        sp[14] += ln.ma;
+    }
+}
+
+} // namespace rj
