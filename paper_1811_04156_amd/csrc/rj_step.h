@@ -319,11 +319,31 @@ template <class R> struct Lane {
     int n;
     double L;    // path length (running sum; refreshed at launch start)
     double lp;   // log p (refreshed at launch start and end)
-    double invw; // 1 / w(n)
-    // statistics of this launch
+    double invw; // 1 / w(n) of the sector tilt
+    double lwm, lw0, lwp; // log w(n - 1), log w(n), log w(n + 1)
+    // statistics of this launch.  The sums that depend on n alone are kept
+    // lazily: `run` counts the counted steps spent at the current n and is
+    // folded in when n changes and at the end of the launch.
+    uint32_t run;
     double a1, a2, sl, sl2;
-    uint32_t cnt, c2, sn, ncap, pp, pb, pd, ap, ab, ad, mp, ma;
+    uint64_t sn;
+    uint32_t cnt, c2, ncap, pp, pb, pd, ap, ab, ad, mp, ma;
 };
+
+template <class R> __device__ __forceinline__ void fold_run(Lane<R>& ln, int n0, int cap, bool tilt) {
+    const uint32_t r = ln.run;
+    const bool at0 = ln.n == n0;
+    ln.cnt += r;
+    ln.c2 += at0 ? r : 0u;
+    ln.sn += (uint64_t)r * (uint64_t)ln.n;
+    ln.ncap += ln.n == cap ? r : 0u;
+    if (tilt) {
+        const double a = (double)r * ln.invw;
+        ln.a1 += a;
+        ln.a2 += at0 ? a : 0.0;
+    }
+    ln.run = 0;
+}
 
 struct StepCtx {
     uint32_t chain, k0, k1;
@@ -451,14 +471,6 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
     // ---------- birth / death through the bi-spherical map ----------
     const bool birth = r[2] < sc.bthresh;
     move = birth ? MV_BIRTH : MV_DEATH;
-    // the tilt values the move can need, fetched early so that their latency
-    // hides behind the proposal arithmetic
-    double lwm = 0.0, lw0 = 0.0, lwp = 0.0;
-    if (sc.logw) {
-        lwm = sc.logw[n - 1];
-        lw0 = sc.logw[n];
-        lwp = sc.logw[n < sc.cap ? n + 1 : n];
-    }
     // S = sum of the cached segment depths, summed afresh in a fixed order (so
     // the chain does not depend on where launches start and end).  The first
     // WB depths are read once into registers (loads issued together) and
@@ -546,11 +558,12 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
     const double Sx = birth ? S : S - (double)ps.w(iA) - (double)ps.w(jv) + (double)AB.tb;
     R lpup = (R)sc.log_pb + Mth<R>::log(AB.tb) - Mth<R>::log((R)Sx);
     R lpdn = (R)sc.log_pd - Mth<R>::log((R)(nx - 1));
-    R dlw = (sc.logw && valid) ? (R)(birth ? lwp - lw0 : lw0 - lwm) : (R)0; // logw[nx + 1] - logw[nx]
+    R dlw = (sc.logw && valid) ? (R)(birth ? ln.lwp - ln.lw0 : ln.lw0 - ln.lwm) : (R)0; // logw[nx + 1] - logw[nx]
     R logAb = (ty - tx) + jac + dlw + lpdn - lpup;
     logA = valid ? (birth ? logAb : -logAb) : Mth<R>::ninf();
     if (logu < logA) {
         accepted = 1;
+        fold_run(ln, T.n0, sc.cap, sc.logw != nullptr); // the steps spent at the old n
         const double dL = (double)sA.len + (double)sB.len - (double)AB.len;
         if (birth) {
             for (int v = n - 1; v >= iB; --v) ps.st(v + 1, ps.ld(v));
@@ -558,13 +571,23 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
             ps.stw(iA, sA.tb);
             ln.L += dL;
             ln.n = n + 1;
+            if (sc.logw) {
+                ln.lwm = ln.lw0;
+                ln.lw0 = ln.lwp;
+                ln.lwp = sc.logw[n + 2 <= sc.cap ? n + 2 : sc.cap];
+            }
         } else {
             for (int v = jv; v <= n - 2; ++v) ps.st(v, ps.ld(v + 1));
             ps.stw(iA, AB.tb);
             ln.L -= dL;
             ln.n = n - 1;
+            if (sc.logw) {
+                ln.lwp = ln.lw0;
+                ln.lw0 = ln.lwm;
+                ln.lwm = sc.logw[n - 2];
+            }
         }
-        ln.invw = sc.logw ? exp(-(birth ? lwp : lwm)) : 1.0;
+        if (sc.logw) ln.invw = exp(-ln.lw0);
     }
 }
 
@@ -640,7 +663,13 @@ __global__ void __launch_bounds__(256) run_kernel(KArgs a) {
     sc.mala_h = a.mala_h;
     sc.sampler = a.sampler;
     sc.logw = a.logw ? a.logw + (size_t)t * (cap + 1) : nullptr;
-    ln.invw = sc.logw ? exp(-sc.logw[ln.n]) : 1.0;
+    ln.invw = 1.0;
+    if (sc.logw) {
+        ln.lwm = sc.logw[ln.n - 1];
+        ln.lw0 = sc.logw[ln.n];
+        ln.lwp = sc.logw[ln.n < cap ? ln.n + 1 : cap];
+        ln.invw = exp(-ln.lw0);
+    }
     const uint64_t step0 = a.step_dev ? *a.step_dev + a.step0 : a.step0; // step0 is the offset then
     int phase = (int)(step0 % (uint64_t)a.cycle_len);
 
@@ -649,38 +678,32 @@ __global__ void __launch_bounds__(256) run_kernel(KArgs a) {
         const bool perturb = phase < a.n_perturb;
         int move, idx, accepted;
         R logA, logu;
+        const bool counted = (int64_t)step >= a.burn_in;
         // the LDS-only instantiation when every active lane's path (and a birth) fits its slots
         if (__all(ln.n < a.V))
             step_body<R, true, MALA>(T, pl, work, ln, sc, step, perturb, move, idx, accepted, logA, logu);
         else
             step_body<R, false, MALA>(T, ps, work, ln, sc, step, perturb, move, idx, accepted, logA, logu);
-        if ((int64_t)step >= a.burn_in) {
-            const int n = ln.n;
-            ln.cnt += 1;
-            ln.c2 += (n == T.n0);
-            if (sc.logw) {
-                ln.a1 += ln.invw;
-                if (n == T.n0) ln.a2 += ln.invw;
-            }
+        {
+            // move counts, branch-free (per-branch updates get merged by the
+            // compiler into a dynamically indexed stack slot)
+            const uint32_t cu = counted ? 1u : 0u, ca = (uint32_t)accepted;
+            const uint32_t ib = cu & (move == MV_BIRTH ? 1u : 0u), id = cu & (move == MV_DEATH ? 1u : 0u);
+            const uint32_t ip = cu - ib - id, im = cu & (move == MV_MALA ? 1u : 0u);
+            ln.pb += ib;
+            ln.pd += id;
+            ln.pp += ip;
+            ln.mp += im;
+            ln.ab += ib & ca;
+            ln.ad += id & ca;
+            ln.ap += ip & ca;
+            ln.ma += im & ca;
+        }
+        if (counted) {
+            ln.run += 1;
             ln.sl += ln.L;
             ln.sl2 += ln.L * ln.L;
-            ln.sn += n;
-            ln.ncap += (n == cap);
-            if (move == MV_BIRTH) {
-                ln.pb += 1;
-                ln.ab += accepted;
-            } else if (move == MV_DEATH) {
-                ln.pd += 1;
-                ln.ad += accepted;
-            } else {
-                ln.pp += 1;
-                ln.ap += accepted;
-            }
-            if (move == MV_MALA) {
-                ln.mp += 1;
-                ln.ma += accepted;
-            }
-            if (a.hist) atomicAdd(a.hist + (size_t)t * (cap + 1) + n, 1u);
+            if (a.hist) atomicAdd(a.hist + (size_t)t * (cap + 1) + ln.n, 1u);
         }
         if (a.trace) {
             double* tr = a.trace + ((size_t)c * a.trace_steps + a.trace_off + s) * RJPATH_TRACE_WORDS;
@@ -693,6 +716,7 @@ __global__ void __launch_bounds__(256) run_kernel(KArgs a) {
         phase = (phase + 1 == a.cycle_len) ? 0 : phase + 1;
     }
 
+    fold_run(ln, T.n0, cap, sc.logw != nullptr);
     // log p of the final path (refreshed once rather than tracked per step)
     if (healthy) ln.lp = full_logp(T, ps, ln.n, ln.L);
     // write back the LDS part, the vertex count, log p and the statistics
@@ -708,7 +732,7 @@ __global__ void __launch_bounds__(256) run_kernel(KArgs a) {
         sp[2] += sc.logw ? ln.a2 : (double)ln.c2;
         sp[3] += ln.sl;
         sp[4] += ln.sl2;
-        sp[5] += ln.sn;
+        sp[5] += (double)ln.sn;
         sp[6] += ln.pp;
         sp[7] += ln.pb;
         sp[8] += ln.pd;
