@@ -40,6 +40,46 @@ FLOP_JUMP_BASE = 208.0      # mean of birth (235) and death (180): proposal, seg
 FLOP_JUMP_PER_VERTEX = 1.0  # birth scan of the cached depths (2 per vertex over half the path, half the jumps)
 
 
+# Sources of the step kernel the benchmark times (the FP32 plain-sampler
+# variant for homogeneous media); the HBM traffic recorded under profiles/ is
+# reported only while their digest matches the one recorded with it.
+KERNEL_SOURCES = ["include/rjpath.h", "paper_1811_04156_amd/csrc/rj_internal.h",
+                  "paper_1811_04156_amd/csrc/rj_device.h", "paper_1811_04156_amd/csrc/rj_step.h",
+                  "paper_1811_04156_amd/csrc/rj_run.h", "paper_1811_04156_amd/csrc/rj_run_f32.hip"]
+TRAFFIC_PROFILE = "profiles/run_kernel_hom_f32_config2_traffic.md"
+
+
+def kernel_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic():
+    """HBM bytes per launch of the step kernel from the FETCH_SIZE / WRITE_SIZE
+    counter runs recorded under profiles/, or None when the kernel sources
+    have changed since (or nothing was recorded)."""
+    try:
+        with open(os.path.join(ROOT, TRAFFIC_PROFILE)) as fh:
+            text = fh.read()
+    except OSError:
+        return None
+    rec = {}
+    for line in text.splitlines():
+        if ":" in line:
+            k, v = line.split(":", 1)
+            rec[k.strip(" -*`")] = v.strip(" `")
+    if rec.get("kernel_source_sha256") != kernel_digest():
+        return None
+    try:
+        return float(rec["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -249,7 +289,7 @@ def main():
         "tuning": {"seconds": t_tune, "block_chains": block or "default (64)", "v_lds": vlds or "default (32)",
                    "tilted_targets": int((s.logw.cpu().numpy().max(1) > 0).sum()) if s.logw is not None else 0},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32, "traffic": None},
+                     "frac": achieved / PEAK_FP32, "traffic": recorded_traffic()},
     }
     if not args.no_extras:
         out["layered_config3"] = layered_throughput()
