@@ -152,8 +152,10 @@ typedef struct {
  * sensor; sampler: RJPATH_PLAIN or RJPATH_MALA (interior steps become joint
  * Langevin moves of all interior vertices with step size mala_h, m^2).
  * block_chains (multiple of 64) and v_lds (vertex slots per chain kept in
- * LDS) select the launch; 0 takes the values tuned for this handle (see
- * rjpath_autotune) or a default.  chunk: steps per kernel launch (0 = all).
+ * LDS; each chain's LDS tile also holds two padding slots, so
+ * (v_lds + 2) * block_chains vertices must fit the LDS left after the media
+ * tables, else RJPATH_EINVAL) select the launch; 0 takes the values tuned for
+ * this handle (see rjpath_autotune) or a default.  chunk: steps per kernel launch (0 = all).
  * trace: NULL or n_chains * steps * RJPATH_TRACE_WORDS doubles.
  * hist: NULL or n_targets * (cap + 1) uint32 counts of the sector n after
  * every post-burn-in step (for tuning the sector tilt).

@@ -387,9 +387,12 @@ int rjpath_run_chains(rjpath_medium* m, const rjpath_targets* t, const rjpath_ch
     if (p->block_chains) block = p->block_chains;
     if (p->v_lds) V = p->v_lds;
     const size_t budget = slot_budget(m, t, c);
-    if ((size_t)V * block * vtx_bytes(c->precision) > budget) {
-        if (p->v_lds) return fail(RJPATH_EINVAL, "v_lds * block_chains exceeds the LDS left after the media tables");
-        V = (int)(budget / (block * vtx_bytes(c->precision)));
+    // each lane's tile holds V slots plus two padding slots
+    if ((size_t)(V + 2) * block * vtx_bytes(c->precision) > budget) {
+        if (p->v_lds)
+            return fail(RJPATH_EINVAL, "(v_lds + 2) * block_chains vertices exceed the LDS left after the media tables");
+        V = (int)(budget / (block * vtx_bytes(c->precision))) - 2;
+        if (V < 1) return fail(RJPATH_EINVAL, "no LDS left for vertex slots after the media tables");
     }
     return run_impl(m, t, c, p, (hipStream_t)stream, block, V);
 }
@@ -404,7 +407,7 @@ int rjpath_autotune(rjpath_medium* m, const rjpath_targets* t, const rjpath_chai
     for (int b : {64, 128, 256})
         for (int v : {4, 8, 12, 16, 24, 32, 48, 64}) {
             int vv = std::min(v, c->cap);
-            if ((size_t)vv * b * vtx_bytes(c->precision) > budget) continue;
+            if ((size_t)(vv + 2) * b * vtx_bytes(c->precision) > budget) continue;
             if (std::find(cand.begin(), cand.end(), std::make_pair(b, vv)) == cand.end()) cand.push_back({b, vv});
         }
     // two passes, the second in reverse order, so that the drift of the chain

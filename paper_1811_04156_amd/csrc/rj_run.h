@@ -9,7 +9,8 @@ namespace rj {
 
 template <class R, int MK, bool MALA, bool SL> static hipError_t launch_run_t(const KArgs& a, int block, hipStream_t s) {
     int grid = (a.C + block - 1) / block;
-    size_t lds = (MK == MK_LAY_LDS ? a.tab_bytes : 0) + (size_t)a.V * block * sizeof(Vtx<R>);
+    // media tables, then one tile of V + SLOT_PAD slots per wave
+    size_t lds = (MK == MK_LAY_LDS ? a.tab_bytes : 0) + (size_t)(a.V + SLOT_PAD) * block * sizeof(Vtx<R>);
     hipLaunchKernelGGL((run_kernel<R, MK, MALA, SL>), dim3(grid), dim3(block), lds, s, a);
     return hipGetLastError();
 }

@@ -46,26 +46,34 @@ template <class R> __device__ __forceinline__ Vtx<R> lds_ld(LdsPtr<R> p) {
 }
 template <class R> __device__ __forceinline__ void lds_st(LdsPtr<R> p, const Vtx<R>& x) { *p = L4<R>{x.x, x.y, x.z, x.w}; }
 
+// LDS layout: each wave owns a tile of V + 2 slots of 64 lanes, slot -1 and
+// slot V being padding, so that a slot stride is a constant (64 vertices) and
+// the LDS-only step can read the neighbours of a vertex (slots -1 .. n + 1,
+// n < V) without clamping their indices: the padding or stale slots it then
+// reads are only ever discarded.
+constexpr int WAVE = 64;
+constexpr int SLOT_PAD = 2;
+
 template <class R, bool LO> struct PathRef {
-    LdsPtr<R> lds; // this lane's slot 0, stride bs
+    LdsPtr<R> lds; // this lane's slot 0, stride WAVE
     Vtx<R>* glb;   // this chain's vertex 0, stride C
-    int bs, V;
+    int V;
     size_t C;
     __device__ __forceinline__ Vtx<R> ld(int v) const {
-        if (LO || v < V) return lds_ld<R>(lds + v * bs);
+        if (LO || v < V) return lds_ld<R>(lds + v * WAVE);
         return glb[(size_t)v * C];
     }
     __device__ __forceinline__ void st(int v, const Vtx<R>& x) const {
-        if (LO || v < V) lds_st<R>(lds + v * bs, x);
+        if (LO || v < V) lds_st<R>(lds + v * WAVE, x);
         else glb[(size_t)v * C] = x;
     }
     __device__ __forceinline__ V3<R> p(int v) const { return pos(ld(v)); }
     __device__ __forceinline__ R w(int v) const {
-        if (LO || v < V) return ((LdsScalar<R>)(lds + v * bs))[3];
+        if (LO || v < V) return ((LdsScalar<R>)(lds + v * WAVE))[3];
         return glb[(size_t)v * C].w;
     }
     __device__ __forceinline__ void stw(int v, R x) const {
-        if (LO || v < V) ((LdsScalar<R>)(lds + v * bs))[3] = x;
+        if (LO || v < V) ((LdsScalar<R>)(lds + v * WAVE))[3] = x;
         else glb[(size_t)v * C].w = x;
     }
 };
@@ -269,12 +277,26 @@ __device__ __forceinline__ double score_stream(const Tgt<R>& T, const P& ps, int
 // whose vertices play different roles do not diverge:
 //   VK_EMIT: the source, log eps(ub) of the first direction;
 //   VK_TURN: an interior vertex, log b + log sigma_sr(ua . ub);
-//   VK_END:  the end point fe, log max(0, -ua . nu) + log rho(nu);
+//   VK_END:  the end point with outward sensor normal nu, log max(0, -ua . nu)
+//            (the angular response log rho(nu) is added by the caller where
+//            it does not cancel);
 //   VK_NONE: no vertex (0).
 // CE / CT / CN: whether the kinds END / EMIT / NONE can occur at the call.
 // ---------------------------------------------------------------------------
 enum { VK_EMIT = 0, VK_TURN = 1, VK_END = 2, VK_NONE = 3 };
 
+struct StepCtx {
+    uint32_t chain, k0, k1;
+    int cap;
+    uint32_t bthresh;
+    float log_pb, log_pd;
+    double sigma, ikappa, e2k, mala_h;
+    int sampler;
+    const double* logw;
+};
+
+
+// log rho(nu) of the paper's angular response (0 for a uniform response)
 template <class R> __device__ __forceinline__ R rho_log(const Tgt<R>& T, V3<R> nu) {
     if (T.dk != RJPATH_DET_PAPER) return (R)0;
     R cr = dot(nu, T.dd);
@@ -285,38 +307,61 @@ template <class R> __device__ __forceinline__ R rho_log(const Tgt<R>& T, V3<R> n
 }
 
 template <class R, bool CE, bool CT, bool CN>
-__device__ __forceinline__ R vtx_term(const Tgt<R>& T, int kind, const LayV<R>& ly, V3<R> ua, V3<R> ub, V3<R> fe) {
+__device__ __forceinline__ R vtx_term(const Tgt<R>& T, int kind, const LayV<R>& ly, V3<R> ua, V3<R> ub, V3<R> nu) {
     V3<R> d = ua - ub;
-    R X = ly.hg1 + ly.g * dot(d, d); // HG denominator, 1 - mu = |ua - ub|^2 / 2
-    V3<R> nu = {(R)0, (R)0, (R)0};
+    const R q = dot(d, d);
+    R X = ly.hg1 + ly.g * q; // HG denominator, 1 - mu = |ua - ub|^2 / 2
     R ce = (R)1;
     if (CE) {
-        V3<R> de = fe - T.eta;
-        nu = Mth<R>::rsqrt(dot(de, de)) * de;
         ce = -dot(ua, nu);
         if (kind == VK_END) X = ce;
     }
     const R lx = Mth<R>::log(X);
-    R turn = ly.logb + ly.hgn - (R)1.5 * lx;
+    R out = ly.logb + ly.hgn - (R)1.5 * lx;
     if (ly.fsl != (R)0) {
-        R q = dot(d, d);
         R hg = ly.hgn - (R)1.5 * lx;
         R sl = ly.sln + ly.sla * Mth<R>::log((R)1 - (R)0.25 * q);
         R m = sl > hg ? sl : hg;
-        turn = ly.logb + m + Mth<R>::log(ly.fsl * Mth<R>::exp(sl - m) + ((R)1 - ly.fsl) * Mth<R>::exp(hg - m));
+        out = ly.logb + m + Mth<R>::log(ly.fsl * Mth<R>::exp(sl - m) + ((R)1 - ly.fsl) * Mth<R>::exp(hg - m));
     }
-    R out = turn;
-    if (CE && kind == VK_END) out = ce > (R)0 ? lx + rho_log(T, nu) : Mth<R>::ninf();
+    if (CE && kind == VK_END) out = ce > (R)0 ? lx : Mth<R>::ninf();
     if (CT && kind == VK_EMIT) out = emit_term(T, ub);
     if (CN && kind == VK_NONE) out = (R)0;
     return out;
 }
+
+// The eight random words of one step: Philox4x32-10 blocks 0 and 1 of the
+// counter (chain, step).  Each branch of the step draws the next step's
+// words while its own path loads are in flight; the chain id passes through
+// an identity lane permutation (quad_perm 0,1,2,3), a convergent operation the
+// compiler may not hoist out of the branch, which would otherwise merge the
+// identical copies above it.
+__device__ __forceinline__ void draw8(const StepCtx& sc, uint64_t step, uint32_t r[8]) {
+    const uint32_t ch = (uint32_t)__builtin_amdgcn_mov_dpp((int)sc.chain, 0xE4, 0xF, 0xF, false);
+    uint32_t q0[4] = {ch, (uint32_t)step, (uint32_t)(step >> 32), 0u};
+    uint32_t q1[4] = {ch, (uint32_t)step, (uint32_t)(step >> 32), 1u};
+    philox4x32_10(q0, sc.k0, sc.k1);
+    philox4x32_10(q1, sc.k0, sc.k1);
+    // (the results pass through the identity permutation as well, so that
+    // the computation is not sunk below the branch either)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        r[i] = (uint32_t)__builtin_amdgcn_mov_dpp((int)q0[i], 0xE4, 0xF, 0xF, false);
+        r[4 + i] = (uint32_t)__builtin_amdgcn_mov_dpp((int)q1[i], 0xE4, 0xF, 0xF, false);
+    }
+}
+
+// Keeps the scheduler from moving instructions across this point: the path
+// loads above it are issued before the independent work below it, which then
+// runs while they are in flight.
+__device__ __forceinline__ void sched_fence() { __builtin_amdgcn_sched_barrier(0); }
 
 // ---------------------------------------------------------------------------
 // Per-lane sampler state and statistics.
 // ---------------------------------------------------------------------------
 template <class R> struct Lane {
     int n;
+    bool live; // the chain steps (a malformed or zero-density chain keeps its state)
     double L;    // path length (running sum; refreshed at launch start)
     double lp;   // log p (refreshed at launch start and end)
     double invw; // 1 / w(n) of the sector tilt
@@ -345,32 +390,18 @@ template <class R> __device__ __forceinline__ void fold_run(Lane<R>& ln, int n0,
     ln.run = 0;
 }
 
-struct StepCtx {
-    uint32_t chain, k0, k1;
-    int cap;
-    uint32_t bthresh;
-    float log_pb, log_pd;
-    double sigma, ikappa, e2k, mala_h;
-    int sampler;
-    const double* logw;
-};
 
 // One step of one lane; returns the move kind, writes log A / accepted / index.
 template <class R, bool LO, bool MALA>
 __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>& ps, const GlobalPath<R>& work,
-                                          Lane<R>& ln, const StepCtx& sc, uint64_t step, bool perturb, int& move,
-                                          int& idx, int& accepted, R& logA, R& logu) {
-    uint32_t r[8];
-    {
-        uint32_t q0[4] = {sc.chain, (uint32_t)step, (uint32_t)(step >> 32), 0u};
-        uint32_t q1[4] = {sc.chain, (uint32_t)step, (uint32_t)(step >> 32), 1u};
-        philox4x32_10(q0, sc.k0, sc.k1);
-        philox4x32_10(q1, sc.k0, sc.k1);
-        r[0] = q0[0]; r[1] = q0[1]; r[2] = q0[2]; r[3] = q0[3];
-        r[4] = q1[0]; r[5] = q1[1]; r[6] = q1[2]; r[7] = q1[3];
-    }
+                                          Lane<R>& ln, const StepCtx& sc, uint64_t step, bool perturb,
+                                          const uint32_t r[8], uint32_t rn[8], int& move, int& idx, int& accepted,
+                                          R& logA, R& logu) {
+    // r: this step's random words; rn receives the next step's (drawn while
+    // this step's path loads are in flight)
     const int n = ln.n;
-    logu = Mth<R>::log(unif<R>(r[1]));
+    // (a chain that is not live rejects every proposal)
+    logu = ln.live ? Mth<R>::log(unif<R>(r[1])) : -Mth<R>::ninf();
     move = MV_NULL;
     idx = -1;
     accepted = 0;
@@ -382,6 +413,7 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
         const bool is_end = (j == n - 1);
         if (MALA && !is_end) {
             // ---------- joint Langevin move of all interior vertices ----------
+            draw8(sc, step + 1, rn);
             move = MV_MALA;
             const R h = (R)sc.mala_h, hh = (R)0.5 * h, sh = Mth<R>::sqrt(h);
             double half_xi2 = 0.0;
@@ -416,9 +448,14 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
         }
         // ---------- single-vertex perturbation: the five-vertex window ----------
         const bool hm2 = j >= 2, hp1 = !is_end, hp2 = j <= n - 3;
-        const V3<R> fm1 = ps.p(j - 1), fo = ps.p(j);
-        // absent neighbours are replaced by harmless stand-ins (loads stay in range)
-        const V3<R> gm2 = ps.p(hm2 ? j - 2 : 0), gp1 = ps.p(hp1 ? j + 1 : 0), gp2 = ps.p(hp2 ? j + 2 : 0);
+        // slots j-2 .. j+2 (absent neighbours are replaced by stand-ins below;
+        // in LDS their slots are readable as they are, elsewhere the indices
+        // are clamped to stay in range)
+        const V3<R> gm2 = ps.p(LO || hm2 ? j - 2 : 0), fm1 = ps.p(j - 1), fo = ps.p(j);
+        const V3<R> gp1 = ps.p(LO || hp1 ? j + 1 : 0), gp2 = ps.p(LO || hp2 ? j + 2 : 0);
+        sched_fence();
+        draw8(sc, step + 1, rn);
+        sched_fence();
         const V3<R> fm2 = hm2 ? gm2 : fm1 - ex;
         const V3<R> fp1 = hp1 ? gp1 : fo + ex;
         const V3<R> fp2 = hp2 ? gp2 : fp1 + ex;
@@ -429,36 +466,38 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
         const R u4 = unif<R>(r[4]), u5 = unif<R>(r[5]);
         const R lg = Mth<R>::log(is_end ? u4 + ((R)1 - u4) * (R)sc.e2k : u4);
         const R c5 = Mth<R>::cos2pi(u5), s5 = Mth<R>::sin2pi(u5);
-        V3<R> fn;
+        V3<R> fn, nu, nn;
         {
             const R rho1 = Mth<R>::sqrt((R)-2 * lg);
             const R rho2 = Mth<R>::sqrt((R)-2 * Mth<R>::log(unif<R>(r[6])));
             const V3<R> xi = {rho1 * c5, rho1 * s5, rho2 * Mth<R>::cos2pi(unif<R>(r[7]))};
             const V3<R> fg = fo + (R)sc.sigma * xi;
-            V3<R> dd = fo - T.eta;
-            V3<R> nu = Mth<R>::rsqrt(dot(dd, dd)) * dd, e2, e3;
+            V3<R> dd = fo - T.eta, e2, e3;
+            nu = Mth<R>::rsqrt(dot(dd, dd)) * dd; // sensor normal at the current end point
             onb(nu, e2, e3);
             const R omw = -lg * (R)sc.ikappa; // 1 - cos
             const R wv = (R)1 - omw;
             const R sw = Mth<R>::sqrt(fmax(omw * ((R)2 - omw), (R)0));
-            const V3<R> fv = T.eta + T.rad * (wv * nu + sw * (c5 * e2 + s5 * e3));
-            fn = is_end ? fv : fg;
+            nn = wv * nu + sw * (c5 * e2 + s5 * e3); // sensor normal at the proposed end point
+            fn = is_end ? T.eta + T.rad * nn : fg;
         }
         const Seg<R> Ao = make_seg(T, fm1, fo), An = make_seg(T, fm1, fn);
         const Seg<R> Bo = make_seg(T, fo, fp1), Bn = make_seg(T, fn, fp1);
-        const V3<R> um = unit_dir(fm2, fm1), up = unit_dir(fp1, fp2);
+        const V3<R> um = unit_dir(fm2, fm1), up = unit_dir(fp1, fp2), nu1 = unit_dir(T.eta, fp1);
         const LayV<R> lm1 = lay_of(T, fm1), lo = lay_of(T, fo), lnw = lay_of(T, fn), lp1 = lay_of(T, fp1);
         const int km1 = hm2 ? VK_TURN : VK_EMIT;
         const int kj = is_end ? VK_END : VK_TURN;
         const int kp1 = !hp1 ? VK_NONE : (hp2 ? VK_TURN : VK_END);
         R d = seg_term(An) - seg_term(Ao);
         d += hp1 ? seg_term(Bn) - seg_term(Bo) : (R)0;
-        d += vtx_term<R, false, true, false>(T, km1, lm1, um, An.u, fm1) -
-             vtx_term<R, false, true, false>(T, km1, lm1, um, Ao.u, fm1);
-        d += vtx_term<R, true, false, false>(T, kj, lnw, An.u, Bn.u, fn) -
-             vtx_term<R, true, false, false>(T, kj, lo, Ao.u, Bo.u, fo);
-        d += vtx_term<R, true, false, true>(T, kp1, lp1, Bn.u, up, fp1) -
-             vtx_term<R, true, false, true>(T, kp1, lp1, Bo.u, up, fp1);
+        d += vtx_term<R, false, true, false>(T, km1, lm1, um, An.u, nu1) -
+             vtx_term<R, false, true, false>(T, km1, lm1, um, Ao.u, nu1);
+        d += vtx_term<R, true, false, false>(T, kj, lnw, An.u, Bn.u, nn) -
+             vtx_term<R, true, false, false>(T, kj, lo, Ao.u, Bo.u, nu);
+        d += vtx_term<R, true, false, true>(T, kp1, lp1, Bn.u, up, nu1) -
+             vtx_term<R, true, false, true>(T, kp1, lp1, Bo.u, up, nu1);
+        // the angular response changes only when the end point itself moves
+        if (T.dk == RJPATH_DET_PAPER && is_end) d += rho_log(T, nn) - rho_log(T, nu);
         logA = d;
         if (logu < logA) {
             accepted = 1;
@@ -479,6 +518,9 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
     R wv[WB];
 #pragma unroll
     for (int v = 0; v < WB; ++v) wv[v] = ps.w(v < n - 1 ? v : 0);
+    sched_fence();
+    draw8(sc, step + 1, rn);
+    sched_fence();
     double S = 0.0;
 #pragma unroll
     for (int v = 0; v < WB; ++v) S += v < n - 1 ? (double)wv[v] : 0.0;
@@ -512,11 +554,24 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
     }
     const int iB = birth ? iA + 1 : iA + 2;
     const bool hprev = iA >= 1, hnext = iB + 1 <= n - 1;
-    const V3<R> A = ps.p(iA), B = ps.p(iB < n ? iB : n - 1);
-    const V3<R> gprev = ps.p(hprev ? iA - 1 : 0), gnext = ps.p(hnext ? iB + 1 : 0);
+    V3<R> A, B, gprev, gnext, fj;
+    if (LO) {
+        // slots iA-1 .. iA+3, read as they are (padding makes all readable)
+        const V3<R> s0 = ps.p(iA - 1), s1 = ps.p(iA), s2 = ps.p(iA + 1), s3 = ps.p(iA + 2), s4 = ps.p(iA + 3);
+        gprev = s0;
+        A = s1;
+        fj = s2; // jv = iA + 1 for a death (unused by a birth)
+        B = birth ? s2 : s3;
+        gnext = birth ? s3 : s4;
+    } else {
+        A = ps.p(iA);
+        B = ps.p(iB < n ? iB : n - 1);
+        gprev = ps.p(hprev ? iA - 1 : 0);
+        gnext = ps.p(hnext ? iB + 1 : 0);
+        fj = ps.p(jv);
+    }
     const V3<R> fprev = hprev ? gprev : A - ex;
     const V3<R> fnext = hnext ? gnext : B + ex;
-    const V3<R> fj = ps.p(jv);
     const Seg<R> AB = make_seg(T, A, B);
     const V3<R> mid = (R)0.5 * (A + B);
     const LayV<R> lm = lay_of(T, mid);
@@ -539,14 +594,15 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
         fv = birth ? fb : fj;
     }
     const Seg<R> sA = make_seg(T, A, fv), sB = make_seg(T, fv, B);
-    const V3<R> up = unit_dir(fprev, A), un = unit_dir(B, fnext);
+    const V3<R> up = unit_dir(fprev, A), un = unit_dir(B, fnext), nuB = unit_dir(T.eta, B);
     const LayV<R> la = lay_of(T, A), lb = lay_of(T, B), lv = lay_of(T, fv);
     const int kA = hprev ? VK_TURN : VK_EMIT, kB = hnext ? VK_TURN : VK_END;
-    const R tx = vtx_term<R, false, true, false>(T, kA, la, up, AB.u, A) +
-                 vtx_term<R, true, false, false>(T, kB, lb, AB.u, un, B);
-    const R ty = vtx_term<R, false, true, false>(T, kA, la, up, sA.u, A) +
-                 vtx_term<R, true, false, false>(T, kB, lb, sB.u, un, B) +
-                 vtx_term<R, false, false, false>(T, VK_TURN, lv, sA.u, sB.u, fv);
+    // (an end point B is the same in x and y: its angular response cancels)
+    const R tx = vtx_term<R, false, true, false>(T, kA, la, up, AB.u, nuB) +
+                 vtx_term<R, true, false, false>(T, kB, lb, AB.u, un, nuB);
+    const R ty = vtx_term<R, false, true, false>(T, kA, la, up, sA.u, nuB) +
+                 vtx_term<R, true, false, false>(T, kB, lb, sB.u, un, nuB) +
+                 vtx_term<R, false, false, false>(T, VK_TURN, lv, sA.u, sB.u, nuB);
     V3<R> dq = sA.u - sB.u;
     R q = dot(dq, dq);
     // segment factors of y over x times |J| / q(s) q(t) q(phi): the inverse-square
@@ -558,7 +614,10 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
     const double Sx = birth ? S : S - (double)ps.w(iA) - (double)ps.w(jv) + (double)AB.tb;
     R lpup = (R)sc.log_pb + Mth<R>::log(AB.tb) - Mth<R>::log((R)Sx);
     R lpdn = (R)sc.log_pd - Mth<R>::log((R)(nx - 1));
-    R dlw = (sc.logw && valid) ? (R)(birth ? ln.lwp - ln.lw0 : ln.lw0 - ln.lwm) : (R)0; // logw[nx + 1] - logw[nx]
+    // logw[nx + 1] - logw[nx] (both differences formed first: a choice between
+    // the loads would become a dynamically indexed stack slot)
+    const double dlw_b = ln.lwp - ln.lw0, dlw_d = ln.lw0 - ln.lwm;
+    R dlw = (sc.logw && valid) ? (R)(birth ? dlw_b : dlw_d) : (R)0;
     R logAb = (ty - tx) + jac + dlw + lpdn - lpup;
     logA = valid ? (birth ? logAb : -logAb) : Mth<R>::ninf();
     if (logu < logA) {
@@ -591,6 +650,52 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
     }
 }
 
+// One sampler step of a lane inside the step loop: the move, then the move
+// counts, the per-step sums, the optional histogram and trace.
+template <class R, bool LO, bool MALA>
+__device__ __forceinline__ void one_step(const KArgs& a, const Tgt<R>& T, const PathRef<R, LO>& ps,
+                                         const GlobalPath<R>& work, Lane<R>& ln, const StepCtx& sc, uint64_t step0,
+                                         int s, int& phase, uint32_t (&rw)[8], uint32_t (&rn)[8], int c, int t) {
+    const uint64_t step = step0 + (uint64_t)s;
+    const bool perturb = phase < a.n_perturb;
+    int move, idx, accepted;
+    R logA, logu;
+    const bool counted = (int64_t)step >= a.burn_in;
+    step_body<R, LO, MALA>(T, ps, work, ln, sc, step, perturb, rw, rn, move, idx, accepted, logA, logu);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) rw[i] = rn[i];
+    {
+        // move counts, branch-free (per-branch updates get merged by the
+        // compiler into a dynamically indexed stack slot)
+        const uint32_t cu = counted ? 1u : 0u, ca = (uint32_t)accepted;
+        const uint32_t ib = cu & (move == MV_BIRTH ? 1u : 0u), id = cu & (move == MV_DEATH ? 1u : 0u);
+        const uint32_t ip = cu - ib - id, im = cu & (move == MV_MALA ? 1u : 0u);
+        ln.pb += ib;
+        ln.pd += id;
+        ln.pp += ip;
+        ln.mp += im;
+        ln.ab += ib & ca;
+        ln.ad += id & ca;
+        ln.ap += ip & ca;
+        ln.ma += im & ca;
+    }
+    if (counted) {
+        ln.run += 1;
+        ln.sl += ln.L;
+        ln.sl2 += ln.L * ln.L;
+        if (a.hist && ln.live) atomicAdd(a.hist + (size_t)t * (a.cap + 1) + ln.n, 1u);
+    }
+    if (a.trace && ln.live) {
+        double* tr = a.trace + ((size_t)c * a.trace_steps + a.trace_off + s) * RJPATH_TRACE_WORDS;
+        tr[0] = move;
+        tr[1] = accepted;
+        tr[2] = idx;
+        tr[3] = (double)logA;
+        tr[4] = (double)logu;
+    }
+    phase = (phase + 1 == a.cycle_len) ? 0 : phase + 1;
+}
+
 // ---------------------------------------------------------------------------
 // The step kernel.  MK: MK_HOM (every medium of the launch is homogeneous: the
 // layer lookups fold away), MK_LAY (layer tables read from HBM) or MK_LAY_LDS
@@ -621,7 +726,9 @@ __global__ void __launch_bounds__(256) run_kernel(KArgs a) {
     const int c = blockIdx.x * bs + tid;
     if (c >= a.C) return;
     const size_t C = (size_t)a.C;
-    LdsPtr<R> lslots = (LdsPtr<R>)((L4<R>*)(smem + tab_bytes) + tid);
+    // this wave's tile, past its leading padding slot
+    LdsPtr<R> lslots = (LdsPtr<R>)((L4<R>*)(smem + tab_bytes) + (size_t)(tid / WAVE) * (a.V + SLOT_PAD) * WAVE +
+                                   WAVE + tid % WAVE);
     const int t = a.target[c];
     Lane<R> ln{};
     ln.n = a.n[c];
@@ -637,12 +744,12 @@ __global__ void __launch_bounds__(256) run_kernel(KArgs a) {
     if (MK == MK_HOM) T.mcnt = 1;
     T.sl = SL;
     if (!SL) T.l0.fsl = (R)0;
-    PathRef<R, false> ps{lslots, (Vtx<R>*)a.verts + c, bs, a.V, C};
-    PathRef<R, true> pl{lslots, (Vtx<R>*)a.verts + c, bs, a.V, C};
+    PathRef<R, false> ps{lslots, (Vtx<R>*)a.verts + c, a.V, C};
+    PathRef<R, true> pl{lslots, (Vtx<R>*)a.verts + c, a.V, C};
     GlobalPath<R> work{a.work ? (Vtx<R>*)a.work + c : nullptr, C};
     // stage the LDS part of the path
     const int nl0 = ln.n < a.V ? ln.n : a.V;
-    for (int v = 0; v < nl0; ++v) lds_st<R>(ps.lds + v * bs, ps.glb[(size_t)v * C]);
+    for (int v = 0; v < nl0; ++v) lds_st<R>(ps.lds + v * WAVE, ps.glb[(size_t)v * C]);
 
     ln.lp = full_logp(T, ps, ln.n, ln.L);
     const bool healthy = isfinite(ln.lp);
@@ -673,47 +780,19 @@ __global__ void __launch_bounds__(256) run_kernel(KArgs a) {
     const uint64_t step0 = a.step_dev ? *a.step_dev + a.step0 : a.step0; // step0 is the offset then
     int phase = (int)(step0 % (uint64_t)a.cycle_len);
 
-    for (int s = 0; s < a.steps && healthy; ++s) {
-        const uint64_t step = step0 + (uint64_t)s;
-        const bool perturb = phase < a.n_perturb;
-        int move, idx, accepted;
-        R logA, logu;
-        const bool counted = (int64_t)step >= a.burn_in;
-        // the LDS-only instantiation when every active lane's path (and a birth) fits its slots
-        if (__all(ln.n < a.V))
-            step_body<R, true, MALA>(T, pl, work, ln, sc, step, perturb, move, idx, accepted, logA, logu);
-        else
-            step_body<R, false, MALA>(T, ps, work, ln, sc, step, perturb, move, idx, accepted, logA, logu);
-        {
-            // move counts, branch-free (per-branch updates get merged by the
-            // compiler into a dynamically indexed stack slot)
-            const uint32_t cu = counted ? 1u : 0u, ca = (uint32_t)accepted;
-            const uint32_t ib = cu & (move == MV_BIRTH ? 1u : 0u), id = cu & (move == MV_DEATH ? 1u : 0u);
-            const uint32_t ip = cu - ib - id, im = cu & (move == MV_MALA ? 1u : 0u);
-            ln.pb += ib;
-            ln.pd += id;
-            ln.pp += ip;
-            ln.mp += im;
-            ln.ab += ib & ca;
-            ln.ad += id & ca;
-            ln.ap += ip & ca;
-            ln.ma += im & ca;
-        }
-        if (counted) {
-            ln.run += 1;
-            ln.sl += ln.L;
-            ln.sl2 += ln.L * ln.L;
-            if (a.hist) atomicAdd(a.hist + (size_t)t * (cap + 1) + ln.n, 1u);
-        }
-        if (a.trace) {
-            double* tr = a.trace + ((size_t)c * a.trace_steps + a.trace_off + s) * RJPATH_TRACE_WORDS;
-            tr[0] = move;
-            tr[1] = accepted;
-            tr[2] = idx;
-            tr[3] = (double)logA;
-            tr[4] = (double)logu;
-        }
-        phase = (phase + 1 == a.cycle_len) ? 0 : phase + 1;
+    ln.live = healthy;
+    uint32_t rw[8], rn[8];
+    draw8(sc, step0, rw);
+    // Every lane runs every step (a lane that is not live only rejects), so
+    // that the step loop is uniform across the wave.  The wave stays in the
+    // LDS-only loop while all its paths fit their slots and falls to the
+    // general loop (slots beyond V in HBM) while some do not.
+    int s = 0;
+    while (s < a.steps) {
+        for (; s < a.steps && __all(ln.n < a.V); ++s)
+            one_step<R, true, MALA>(a, T, pl, work, ln, sc, step0, s, phase, rw, rn, c, t);
+        for (; s < a.steps && !__all(ln.n < a.V); ++s)
+            one_step<R, false, MALA>(a, T, ps, work, ln, sc, step0, s, phase, rw, rn, c, t);
     }
 
     fold_run(ln, T.n0, cap, sc.logw != nullptr);
@@ -721,7 +800,7 @@ __global__ void __launch_bounds__(256) run_kernel(KArgs a) {
     if (healthy) ln.lp = full_logp(T, ps, ln.n, ln.L);
     // write back the LDS part, the vertex count, log p and the statistics
     const int nw = ln.n < a.V ? ln.n : a.V;
-    for (int v = 0; v < nw; ++v) ps.glb[(size_t)v * C] = lds_ld<R>(ps.lds + v * bs);
+    for (int v = 0; v < nw; ++v) ps.glb[(size_t)v * C] = lds_ld<R>(ps.lds + v * WAVE);
     a.n[c] = ln.n;
     a.logp[c] = ln.lp;
     if (healthy) {
