@@ -305,11 +305,38 @@ size_t slot_budget(const rjpath_medium* m, const rjpath_targets* t, const rjpath
     return LDS_MAX - make_args(m, t, c).tab_bytes;
 }
 
-void default_launch(int cap, int prec, int& block, int& V) {
-    // one wave per block with 32 slots (16 in FP64) per lane: the fastest
-    // configuration measured on the batched homogeneous workload
+// Compute units of the current device (the occupancy rule below needs them).
+int device_cus() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) return 256;
+    return cus;
+}
+
+// Default launch configuration.  One wave per SIMD issues at most about one
+// instruction per two issue slots of its SIMD, and a second resident wave
+// nearly doubles the SIMD's throughput (measured on gfx950).  So:
+//  - fewer chains than two waves per SIMD: one 64-chain wave per block with
+//    32 slots per lane (16 in FP64), the fastest configuration measured for
+//    one wave per SIMD;
+//  - otherwise (FP32): 256-chain blocks with as many slots as let two blocks
+//    (eight waves) share a CU's LDS, so that two waves are resident per SIMD
+//    (the step kernel's register use allows two).
+void default_launch(const rjpath_chains* c, size_t tab_bytes, int& block, int& V) {
+    const int cap = c->cap;
     block = 64;
-    V = std::min(cap, prec == RJPATH_F64 ? 16 : 32);
+    V = std::min(cap, c->precision == RJPATH_F64 ? 16 : 32);
+    const long long two_waves = 2LL * 4 * device_cus() * 64;
+    if (c->precision == RJPATH_F32 && (long long)c->n_chains >= two_waves) {
+        const size_t per_block = LDS_MAX / 2;
+        if (per_block > tab_bytes) {
+            const long long slots = (long long)((per_block - tab_bytes) / (256 * vtx_bytes(RJPATH_F32))) - 2;
+            if (slots >= 8) {
+                block = 256;
+                V = (int)std::min<long long>(std::min(cap, 32), slots);
+            }
+        }
+    }
 }
 
 int run_impl(rjpath_medium* m, const rjpath_targets* t, const rjpath_chains* c, const rjpath_run_params* p,
@@ -378,7 +405,7 @@ int rjpath_run_chains(rjpath_medium* m, const rjpath_targets* t, const rjpath_ch
     if (r) return r;
     if (p->steps == 0) return RJPATH_OK;
     int block, V;
-    default_launch(c->cap, c->precision, block, V);
+    default_launch(c, make_args(m, t, c).tab_bytes, block, V);
     auto it = m->tuned.find(TuneKey{c->cap, c->precision, p->sampler});
     if (it != m->tuned.end()) {
         block = it->second.first;
