@@ -331,30 +331,15 @@ __device__ __forceinline__ R vtx_term(const Tgt<R>& T, int kind, const LayV<R>& 
 }
 
 // The eight random words of one step: Philox4x32-10 blocks 0 and 1 of the
-// counter (chain, step).  Each branch of the step draws the next step's
-// words while its own path loads are in flight; the chain id passes through
-// an identity lane permutation (quad_perm 0,1,2,3), a convergent operation the
-// compiler may not hoist out of the branch, which would otherwise merge the
-// identical copies above it.
+// counter (chain, step).
 __device__ __forceinline__ void draw8(const StepCtx& sc, uint64_t step, uint32_t r[8]) {
-    const uint32_t ch = (uint32_t)__builtin_amdgcn_mov_dpp((int)sc.chain, 0xE4, 0xF, 0xF, false);
-    uint32_t q0[4] = {ch, (uint32_t)step, (uint32_t)(step >> 32), 0u};
-    uint32_t q1[4] = {ch, (uint32_t)step, (uint32_t)(step >> 32), 1u};
+    uint32_t q0[4] = {sc.chain, (uint32_t)step, (uint32_t)(step >> 32), 0u};
+    uint32_t q1[4] = {sc.chain, (uint32_t)step, (uint32_t)(step >> 32), 1u};
     philox4x32_10(q0, sc.k0, sc.k1);
     philox4x32_10(q1, sc.k0, sc.k1);
-    // (the results pass through the identity permutation as well, so that
-    // the computation is not sunk below the branch either)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        r[i] = (uint32_t)__builtin_amdgcn_mov_dpp((int)q0[i], 0xE4, 0xF, 0xF, false);
-        r[4 + i] = (uint32_t)__builtin_amdgcn_mov_dpp((int)q1[i], 0xE4, 0xF, 0xF, false);
-    }
+    r[0] = q0[0]; r[1] = q0[1]; r[2] = q0[2]; r[3] = q0[3];
+    r[4] = q1[0]; r[5] = q1[1]; r[6] = q1[2]; r[7] = q1[3];
 }
-
-// Keeps the scheduler from moving instructions across this point: the path
-// loads above it are issued before the independent work below it, which then
-// runs while they are in flight.
-__device__ __forceinline__ void sched_fence() { __builtin_amdgcn_sched_barrier(0); }
 
 // ---------------------------------------------------------------------------
 // Per-lane sampler state and statistics.
@@ -394,11 +379,10 @@ template <class R> __device__ __forceinline__ void fold_run(Lane<R>& ln, int n0,
 // One step of one lane; returns the move kind, writes log A / accepted / index.
 template <class R, bool LO, bool MALA>
 __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>& ps, const GlobalPath<R>& work,
-                                          Lane<R>& ln, const StepCtx& sc, uint64_t step, bool perturb,
-                                          const uint32_t r[8], uint32_t rn[8], int& move, int& idx, int& accepted,
-                                          R& logA, R& logu) {
-    // r: this step's random words; rn receives the next step's (drawn while
-    // this step's path loads are in flight)
+                                          Lane<R>& ln, const StepCtx& sc, uint64_t step, bool perturb, int& move,
+                                          int& idx, int& accepted, R& logA, R& logu) {
+    uint32_t r[8];
+    draw8(sc, step, r);
     const int n = ln.n;
     // (a chain that is not live rejects every proposal)
     logu = ln.live ? Mth<R>::log(unif<R>(r[1])) : -Mth<R>::ninf();
@@ -413,7 +397,6 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
         const bool is_end = (j == n - 1);
         if (MALA && !is_end) {
             // ---------- joint Langevin move of all interior vertices ----------
-            draw8(sc, step + 1, rn);
             move = MV_MALA;
             const R h = (R)sc.mala_h, hh = (R)0.5 * h, sh = Mth<R>::sqrt(h);
             double half_xi2 = 0.0;
@@ -453,9 +436,6 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
         // are clamped to stay in range)
         const V3<R> gm2 = ps.p(LO || hm2 ? j - 2 : 0), fm1 = ps.p(j - 1), fo = ps.p(j);
         const V3<R> gp1 = ps.p(LO || hp1 ? j + 1 : 0), gp2 = ps.p(LO || hp2 ? j + 2 : 0);
-        sched_fence();
-        draw8(sc, step + 1, rn);
-        sched_fence();
         const V3<R> fm2 = hm2 ? gm2 : fm1 - ex;
         const V3<R> fp1 = hp1 ? gp1 : fo + ex;
         const V3<R> fp2 = hp2 ? gp2 : fp1 + ex;
@@ -514,16 +494,18 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
     // the chain does not depend on where launches start and end).  The first
     // WB depths are read once into registers (loads issued together) and
     // serve both the sum and the segment scan.
-    constexpr int WB = 8;
+    // (16 cover all but rare long paths of the batched workloads; the FP64
+    // and Langevin variants keep 8 so that their registers still allow two
+    // resident waves per SIMD where they did)
+    constexpr int WB = (sizeof(R) == 4 && !MALA) ? 16 : 8;
     R wv[WB];
 #pragma unroll
     for (int v = 0; v < WB; ++v) wv[v] = ps.w(v < n - 1 ? v : 0);
-    sched_fence();
-    draw8(sc, step + 1, rn);
-    sched_fence();
+#pragma unroll
+    for (int v = 0; v < WB; ++v) wv[v] = v < n - 1 ? wv[v] : (R)0; // (adding 0 leaves a sum unchanged)
     double S = 0.0;
 #pragma unroll
-    for (int v = 0; v < WB; ++v) S += v < n - 1 ? (double)wv[v] : 0.0;
+    for (int v = 0; v < WB; ++v) S += (double)wv[v];
     for (int v = WB; v < n - 1; ++v) S += (double)ps.w(v);
     const bool valid = birth ? (n < sc.cap && S > 0.0) : (n > 2);
     int iA = 0, jv = 1;
@@ -535,10 +517,11 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
             const double tgt = (double)unif<double>(r[0]) * S;
             double cum = 0.0;
             int k = 0;
+            // (past the path the cumulative sum stays at S > U S: no count)
 #pragma unroll
             for (int v = 0; v < WB; ++v) {
-                cum += v < n - 1 ? (double)wv[v] : 0.0;
-                k += (v < n - 1 && cum <= tgt) ? 1 : 0;
+                cum += (double)wv[v];
+                k += cum <= tgt ? 1 : 0;
             }
             for (int v = WB; v < n - 1; ++v) {
                 cum += (double)ps.w(v);
@@ -655,15 +638,13 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
 template <class R, bool LO, bool MALA>
 __device__ __forceinline__ void one_step(const KArgs& a, const Tgt<R>& T, const PathRef<R, LO>& ps,
                                          const GlobalPath<R>& work, Lane<R>& ln, const StepCtx& sc, uint64_t step0,
-                                         int s, int& phase, uint32_t (&rw)[8], uint32_t (&rn)[8], int c, int t) {
+                                         int s, int& phase, int c, int t) {
     const uint64_t step = step0 + (uint64_t)s;
     const bool perturb = phase < a.n_perturb;
     int move, idx, accepted;
     R logA, logu;
     const bool counted = (int64_t)step >= a.burn_in;
-    step_body<R, LO, MALA>(T, ps, work, ln, sc, step, perturb, rw, rn, move, idx, accepted, logA, logu);
-#pragma unroll
-    for (int i = 0; i < 8; ++i) rw[i] = rn[i];
+    step_body<R, LO, MALA>(T, ps, work, ln, sc, step, perturb, move, idx, accepted, logA, logu);
     {
         // move counts, branch-free (per-branch updates get merged by the
         // compiler into a dynamically indexed stack slot)
@@ -781,8 +762,6 @@ __global__ void __launch_bounds__(256) run_kernel(KArgs a) {
     int phase = (int)(step0 % (uint64_t)a.cycle_len);
 
     ln.live = healthy;
-    uint32_t rw[8], rn[8];
-    draw8(sc, step0, rw);
     // Every lane runs every step (a lane that is not live only rejects), so
     // that the step loop is uniform across the wave.  The wave stays in the
     // LDS-only loop while all its paths fit their slots and falls to the
@@ -790,9 +769,9 @@ __global__ void __launch_bounds__(256) run_kernel(KArgs a) {
     int s = 0;
     while (s < a.steps) {
         for (; s < a.steps && __all(ln.n < a.V); ++s)
-            one_step<R, true, MALA>(a, T, pl, work, ln, sc, step0, s, phase, rw, rn, c, t);
+            one_step<R, true, MALA>(a, T, pl, work, ln, sc, step0, s, phase, c, t);
         for (; s < a.steps && !__all(ln.n < a.V); ++s)
-            one_step<R, false, MALA>(a, T, ps, work, ln, sc, step0, s, phase, rw, rn, c, t);
+            one_step<R, false, MALA>(a, T, ps, work, ln, sc, step0, s, phase, c, t);
     }
 
     fold_run(ln, T.n0, cap, sc.logw != nullptr);
