@@ -91,6 +91,9 @@ def parse():
     ap.add_argument("--no-extras", action="store_true", help="skip the layered and grad-vs-plain measurements")
     ap.add_argument("--autotune", action="store_true",
                     help="time the launch configurations first (default: the library's measured default)")
+    ap.add_argument("--occupancy-probe", action="store_true",
+                    help="also time the config-2 kernel (cap 12, all paths in LDS) at one and two resident "
+                         "waves per SIMD (65,536 and 131,072 chains)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one plain device copy of this size (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -165,6 +168,32 @@ def grad_vs_plain(steps=3000, chunk=500):
         if h is not None:
             out[name].update(mala_h=h, mala_acceptance=float(st[:, 14].sum() / max(1.0, st[:, 13].sum())))
     out["ess_ratio_mala_over_plain"] = out["mala"]["ess_per_s"] / out["plain"]["ess_per_s"]
+    return out
+
+
+def occupancy_probe(steps=1000):
+    """The step kernel on config 2's media with cap 12 (every path fits its 12
+    LDS slots, so the work per chain-step is the same at every occupancy), at
+    one resident wave per SIMD (65,536 chains) and two (131,072 chains): how
+    much of a SIMD's issue rate one wave leaves unused."""
+    import torch
+    from paper_1811_04156_amd import workloads as W
+    from paper_1811_04156_amd.rjpath import Sampler
+    out = {}
+    for pg in (256, 512):
+        w = W.config2(per_group=pg, cap=12)
+        w["burn_in"] = 0
+        s = Sampler(w, device="cuda:0", precision="f32")
+        s.run(2000, block=64, v_lds=12)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            s.run(steps, block=64, v_lds=12)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / 3
+        out[f"{s.C}_chains"] = {"ms_per_launch": dt * 1e3, "ns_per_chain_step": dt * 1e9 / (s.C * steps)}
+    a, b = out["65536_chains"], out["131072_chains"]
+    out["two_wave_speedup_per_chain_step"] = a["ns_per_chain_step"] / b["ns_per_chain_step"]
     return out
 
 
@@ -294,6 +323,8 @@ def main():
     if not args.no_extras:
         out["layered_config3"] = layered_throughput()
         out["grad_vs_plain"] = grad_vs_plain()
+    if args.occupancy_probe:
+        out["occupancy_probe"] = occupancy_probe()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(out), flush=True)
