@@ -135,7 +135,7 @@ def test_fp64_free_run_matches_oracle(rj):
     gst = s.stats.cpu().numpy()
     counts = [0, 5, 6, 7, 8, 9, 10, 11, 12]
     assert np.array_equal(gst[:, counts], ostats[:, counts])
-    # path-length sums: the device keeps L in 2^-32 m fixed point
+    # path-length sums: the device keeps L as an FP64 running sum (grouping differs)
     assert np.allclose(gst, ostats, rtol=1e-9, atol=1e-9)
     # the device's intensity estimator on the same statistics
     res = s.intensity(groups=16)
@@ -237,6 +237,28 @@ def test_launch_configuration_and_resume_invariance(rj):
     assert torch.allclose(ref.stats, other.stats, rtol=1e-13, atol=0)
     # the cached log p is refreshed at every launch start (FP32 terms)
     assert torch.allclose(ref.logp, other.logp, rtol=1e-6, atol=1e-4)
+
+
+@pytest.mark.parametrize("kind", ["homog", "layered"])
+def test_default_launch_at_two_waves_per_simd(rj, kind):
+    """With two waves' worth of chains per SIMD the default launch switches to
+    256-chain blocks with fewer LDS slots; the chains must follow exactly the
+    trajectories of the one-wave launch (64-chain blocks, 32 slots)."""
+    if kind == "homog":
+        w = W.config2(groups=256, per_group=512, cap=64)
+    else:
+        w = W.layered_pairs(pairs=64, chains=1 << 17, cap=64)
+    w["burn_in"] = 0
+    a = rj.Sampler(w, precision="f32")
+    b = rj.Sampler(w, precision="f32")
+    a.run(300)
+    b.run(300, block=64, v_lds=32)
+    torch.cuda.synchronize()
+    assert torch.equal(a.n, b.n)
+    used = (torch.arange(a.cap, device=a.n.device)[:, None] < a.n[None, :])[..., None]
+    assert torch.equal(a.verts[..., :3] * used, b.verts[..., :3] * used)
+    assert torch.equal(a.stats[:, [0, 5, 6, 7, 8, 9, 10, 11]], b.stats[:, [0, 5, 6, 7, 8, 9, 10, 11]])
+    assert int(a.stats[:, 10].sum().item()) > 0  # births were accepted
 
 
 def test_anchor_parity(rj):
