@@ -204,16 +204,34 @@ template <class R> __device__ __forceinline__ V3<R> dunit(V3<R> u, R len, V3<R> 
     return il * (c - dot(u, c) * u);
 }
 
-template <class R, class P, class Emit>
-__device__ __forceinline__ double score_stream(const Tgt<R>& T, const P& ps, int n, Emit emit) {
-    V3<R> z = {(R)0, (R)0, (R)0};
-    V3<R> gA = z, gB = z, gC = z; // vertices k-2, k-1, k
-    V3<R> fprev = ps.p(0), fcur;
-    Seg<R> sprev;
-    double lp = 0.0;
-    bool zero = false;
-    for (int k = 1; k < n; ++k) {
-        fcur = ps.p(k);
+// The streaming score as a walker fed one vertex at a time, so that two
+// walks (the current path and a proposal generated from the first walk's
+// gradients) can advance in one loop.  step(f_k) consumes vertex k >= 1 and
+// returns true with the finished gradient of vertex k-2 when k >= 2;
+// finish() adds the end term and returns log p, with the gradients of
+// vertices n-2 and n-1.
+template <class R> struct ScoreWalker {
+    V3<R> gA, gB; // gradients of vertices k-2, k-1 in progress
+    V3<R> fprev;
+    V3<R> uprev; // direction and length of the previous segment
+    R lprev;
+    double lp;
+    bool zero;
+    int k; // next vertex to consume
+
+    __device__ __forceinline__ void init(V3<R> f0) {
+        const V3<R> z = {(R)0, (R)0, (R)0};
+        gA = z;
+        gB = z;
+        fprev = f0;
+        uprev = z;
+        lprev = (R)0;
+        lp = 0.0;
+        zero = false;
+        k = 1;
+    }
+
+    __device__ __forceinline__ bool step(const Tgt<R>& T, V3<R> fcur, V3<R>& gout) {
         Seg<R> s = make_seg(T, fprev, fcur);
         zero |= !(s.len > (R)0);
         lp += (double)seg_term(s);
@@ -221,7 +239,8 @@ __device__ __forceinline__ double score_stream(const Tgt<R>& T, const P& ps, int
         seg_depth_grad(T, fprev, fcur, s, dP, dQ);
         R il2 = (R)2 / s.len;
         gB = gB - dP + il2 * s.u;
-        gC = gC - dQ - il2 * s.u;
+        const V3<R> z = {(R)0, (R)0, (R)0};
+        V3<R> gC = z - dQ - il2 * s.u; // vertex k
         if (k == 1) {
             lp += (double)emit_term(T, s.u);
             if (T.ek == RJPATH_EMIT_VMF) {
@@ -232,42 +251,60 @@ __device__ __forceinline__ double score_stream(const Tgt<R>& T, const P& ps, int
         } else {
             // turn (and scattering density) at vertex k-1 between sprev and s
             const LayV<R> ly = lay_of(T, fprev);
-            V3<R> dd = sprev.u - s.u;
-            lp += (double)(ly.logb + turn_term(ly, sprev.u, s.u));
+            V3<R> dd = uprev - s.u;
+            lp += (double)(ly.logb + turn_term(ly, uprev, s.u));
             R h = dturn_dmu(ly, dot(dd, dd));
-            V3<R> da = dunit(sprev.u, sprev.len, s.u);
-            V3<R> db = dunit(s.u, s.len, sprev.u);
+            V3<R> da = dunit(uprev, lprev, s.u);
+            V3<R> db = dunit(s.u, s.len, uprev);
             gA = gA - h * da;
             gB = gB + h * da - h * db;
             gC = gC + h * db;
-            emit(k - 2, gA);
         }
+        const bool done = k >= 2;
+        gout = gA;
         gA = gB;
         gB = gC;
-        gC = z;
-        sprev = s;
+        uprev = s.u;
+        lprev = s.len;
         fprev = fcur;
+        ++k;
+        return done;
     }
-    // end term on segment n-2 and the end point (gA = vertex n-2, gB = vertex n-1)
-    lp += (double)end_term(T, sprev.u, fprev);
-    V3<R> d = fprev - T.eta;
-    R dn2 = dot(d, d);
-    R idn = Mth<R>::rsqrt(dn2);
-    V3<R> nu = idn * d;
-    R c = -dot(sprev.u, nu);
-    R ic = (R)1 / c;
-    V3<R> dcr = (R)-1 * dunit(sprev.u, sprev.len, nu);
-    V3<R> dcd = (R)-1 * dunit(nu, dn2 * idn, sprev.u);
-    gA = gA - ic * dcr;
-    gB = gB + ic * dcr + ic * dcd;
-    if (T.dk == RJPATH_DET_PAPER) {
-        R cr = dot(nu, T.dd);
-        R th = tanh((R)2 * cr + (R)0.7);
-        gB = gB + ((R)3 - (R)2 * th) * dunit(nu, dn2 * idn, T.dd);
+
+    __device__ __forceinline__ double finish(const Tgt<R>& T, V3<R>& g_nm2, V3<R>& g_nm1) {
+        // end term on segment n-2 and the end point (gA = vertex n-2, gB = vertex n-1)
+        lp += (double)end_term(T, uprev, fprev);
+        V3<R> d = fprev - T.eta;
+        R dn2 = dot(d, d);
+        R idn = Mth<R>::rsqrt(dn2);
+        V3<R> nu = idn * d;
+        R c = -dot(uprev, nu);
+        R ic = (R)1 / c;
+        V3<R> dcr = (R)-1 * dunit(uprev, lprev, nu);
+        V3<R> dcd = (R)-1 * dunit(nu, dn2 * idn, uprev);
+        gA = gA - ic * dcr;
+        gB = gB + ic * dcr + ic * dcd;
+        if (T.dk == RJPATH_DET_PAPER) {
+            R cr = dot(nu, T.dd);
+            R th = tanh((R)2 * cr + (R)0.7);
+            gB = gB + ((R)3 - (R)2 * th) * dunit(nu, dn2 * idn, T.dd);
+        }
+        g_nm2 = gA;
+        g_nm1 = gB;
+        return zero ? -__builtin_inf() : lp;
     }
-    if (n >= 3) emit(n - 2, gA);
-    emit(n - 1, gB);
-    if (zero) lp = -__builtin_inf();
+};
+
+template <class R, class P, class Emit>
+__device__ __forceinline__ double score_stream(const Tgt<R>& T, const P& ps, int n, Emit emit) {
+    ScoreWalker<R> w;
+    w.init(ps.p(0));
+    V3<R> g, g2;
+    for (int k = 1; k < n; ++k)
+        if (w.step(T, ps.p(k), g)) emit(k - 2, g);
+    const double lp = w.finish(T, g, g2);
+    if (n >= 3) emit(n - 2, g);
+    emit(n - 1, g2);
     return lp;
 }
 
@@ -399,10 +436,23 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
             // ---------- joint Langevin move of all interior vertices ----------
             move = MV_MALA;
             const R h = (R)sc.mala_h, hh = (R)0.5 * h, sh = Mth<R>::sqrt(h);
-            double half_xi2 = 0.0;
-            double lpx = score_stream(T, ps, n, [&](int k, V3<R> g) {
-                Vtx<R> x = ps.ld(k);
-                V3<R> y = pos(x);
+            // One loop walks the current path x and the proposal y together:
+            // the walk over x finishes the gradient of vertex k, which gives
+            // y_k, which the walk over y consumes at once (it finishes the
+            // gradient of y_{k-2}).  y goes to the work buffer only for the
+            // copy-back on acceptance.
+            double half_xi2 = 0.0, rev = 0.0;
+            ScoreWalker<R> wx, wy;
+            const V3<R> x0 = ps.p(0);
+            wx.init(x0);
+            wy.init(x0);
+            // y_k, y_{k-1}, y_{k-2} of the last vertex k fed to the y walk, kept
+            // as scalars so that the ring stays in registers
+            R y0x = x0.x, y0y = x0.y, y0z = x0.z, y1x = x0.x, y1y = x0.y, y1z = x0.z;
+            R y2x = x0.x, y2y = x0.y, y2z = x0.z;
+            // y_k from the gradient of x at vertex k (interior: Langevin step)
+            auto make_y = [&](int k, V3<R> g) __attribute__((always_inline)) {
+                V3<R> y = ps.p(k);
                 if (k >= 1 && k <= n - 2) {
                     uint32_t q[4] = {sc.chain, (uint32_t)step, (uint32_t)(step >> 32), 2u + (uint32_t)k};
                     philox4x32_10(q, sc.k0, sc.k1);
@@ -410,16 +460,41 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
                     box_muller3<R>(q[0], q[1], q[2], q[3], xi);
                     half_xi2 += 0.5 * (double)dot(xi, xi);
                     y = y + hh * g + sh * xi;
+                    work.glb[(size_t)k * work.C] = Vtx<R>{y.x, y.y, y.z, (R)0};
                 }
-                work.glb[(size_t)k * work.C] = Vtx<R>{y.x, y.y, y.z, (R)0};
-            });
-            double rev = 0.0;
-            double lpy = score_stream(T, work, n, [&](int k, V3<R> g) {
+                return y;
+            };
+            // the reverse-proposal term of vertex k from the gradient of y there
+            auto rev_term = [&](int k, V3<R> g, V3<R> yk) __attribute__((always_inline)) {
                 if (k >= 1 && k <= n - 2) {
-                    V3<R> d = ps.p(k) - work.p(k) - hh * g;
+                    V3<R> d = ps.p(k) - yk - hh * g;
                     rev += (double)dot(d, d) / (2.0 * (double)h);
                 }
-            });
+            };
+            auto feed_y = [&](V3<R> y) __attribute__((always_inline)) {
+                y2x = y1x;
+                y2y = y1y;
+                y2z = y1z;
+                y1x = y0x;
+                y1y = y0y;
+                y1z = y0z;
+                y0x = y.x;
+                y0y = y.y;
+                y0z = y.z;
+                const int ky = wy.k;
+                V3<R> gy;
+                if (wy.step(T, y, gy)) rev_term(ky - 2, gy, V3<R>{y2x, y2y, y2z});
+            };
+            V3<R> g, g2;
+            for (int k = 1; k < n; ++k) {
+                if (wx.step(T, ps.p(k), g) && k >= 3) feed_y(make_y(k - 2, g));
+            }
+            // (vertex 0 never moves; its gradient is not needed)
+            const double lpx = wx.finish(T, g, g2);
+            if (n >= 3) feed_y(make_y(n - 2, g));
+            feed_y(make_y(n - 1, g2));
+            const double lpy = wy.finish(T, g, g2);
+            if (n >= 3) rev_term(n - 2, g, V3<R>{y1x, y1y, y1z});
             double la = lpy - lpx - rev + half_xi2;
             logA = isfinite(lpy) ? (R)la : Mth<R>::ninf();
             if (logu < logA) {
