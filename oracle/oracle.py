@@ -18,7 +18,7 @@ SRC = os.path.join(HERE, "rjoracle.cpp")
 LIB = os.path.join(HERE, "librjoracle.so")
 
 NSTAT = 16
-MOVE_NAMES = ["interior", "end", "birth", "death", "mala", "null"]
+MOVE_NAMES = ["interior", "end", "birth", "death", "mala", "null", "local_mala"]
 
 
 def build(force: bool = True) -> str:
@@ -55,10 +55,12 @@ def lib():
             "orc_beta": (d, [p, i, p, p]),
             "orc_grad": (None, [p, i, i, p, p, p, p, p]),
             "orc_step": (None, [p, p, p, u32, i, p, p, p]),
+            "orc_propose": (d, [p, p, p, i, i, i, p, i, p, p, p, p]),
             "orc_run": (None, [p, p, p, i, p, p, p, p, p, p, i]),
             "orc_anchor_I2": (d, [p, i, i, i]),
             "orc_anchor_I3": (d, [p, i, i, i, i, i, i]),
-            "orc_trace": (None, [p, i, u64, i64, d, i, p]),
+            "orc_trace": (None, [p, i, u64, i64, d, d, i, p]),
+            "orc_trace_tallies": (i, []),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -222,6 +224,18 @@ class Oracle:
         lib().orc_step(self.h, _ptr(ip), _ptr(dp), int(chain), int(t), C.byref(nn), _ptr(v), _ptr(rec))
         return nn.value, v[: nn.value].copy(), rec
 
+    def propose(self, run, t, verts, kind, idx, u):
+        """One proposal from continuous draws u (see orc_propose): returns
+        (proposed path or None, log A, move code)."""
+        ip, dp = self._params(run, 0, 1)
+        v = _f64(verts).reshape(-1, 3)
+        uu = _f64(u)
+        y = np.zeros((len(v) + 1, 3))
+        ny, mv = C.c_int(0), C.c_int(0)
+        la = lib().orc_propose(self.h, _ptr(ip), _ptr(dp), int(t), int(kind), len(v), _ptr(v), int(idx), _ptr(uu),
+                               C.byref(ny), _ptr(y), C.byref(mv))
+        return (y[: ny.value].copy() if ny.value else None), la, mv.value
+
     def run(self, run, state, steps, step0=0, trace=False, threads=None, chain_ids=None):
         """Advance every chain of ``state`` (dict with target, n, verts (C, cap, 3)) by
         ``steps`` steps in place; returns per-chain stats (C, 16) and the optional
@@ -250,12 +264,23 @@ class Oracle:
     def trace(self, t, nphot, seed=12345, esc=None, threads=None):
         """Analog tracer: (mean, se) of the detected weight per photon and the
         per-scatter-count split (8, 2)."""
-        out = np.zeros(18)
+        r = self.trace_full(t, nphot, seed, esc, threads)
+        return r["I"][0], r["I"][1], r["bucket"]
+
+    def trace_full(self, t, nphot, seed=12345, esc=None, threads=None, lbin=0.0):
+        """Analog tracer, every tally as (mean, se) per photon:
+        I (2,) detected weight; bucket (8, 2) weight by scatter count (last: >= 7);
+        bucket_L (8, 2) weight x path length by scatter count; wL (2,) weight x
+        path length; wN (2,) weight x scatter count; lhist (48, 2) weight by
+        path-length bin of width lbin (last bin: overflow)."""
+        K = lib().orc_trace_tallies()
+        out = np.zeros(2 * K)
         if esc is None:
             esc = 2000.0
         th = threads or (os.cpu_count() or 1)
-        lib().orc_trace(self.h, int(t), seed, int(nphot), float(esc), int(th), _ptr(out))
-        return out[0], out[1], out[2:].reshape(8, 2)
+        lib().orc_trace(self.h, int(t), seed, int(nphot), float(esc), float(lbin), int(th), _ptr(out))
+        o = out.reshape(K, 2)
+        return dict(I=o[0], bucket=o[1:9], bucket_L=o[9:17], wL=o[17], wN=o[18], lhist=o[19:])
 
 
 def initial_state(w, chains=None):

@@ -326,11 +326,11 @@ struct Params {
     int cycle_len, n_perturb;
     uint32_t birth_thresh; // birth iff draw < birth_thresh (birth fraction * 2^32)
     double sigma, kappa_end;
-    int sampler; // 0 plain, 1 MALA interior moves
+    int sampler; // 0 plain, 1 joint Langevin move of all interior vertices, 2 single-vertex Langevin move
     double mala_h;
 };
 
-enum { MV_INTERIOR = 0, MV_END = 1, MV_BIRTH = 2, MV_DEATH = 3, MV_MALA = 4, MV_NULL = 5 };
+enum { MV_INTERIOR = 0, MV_END = 1, MV_BIRTH = 2, MV_DEATH = 3, MV_MALA = 4, MV_NULL = 5, MV_LMALA = 6 };
 enum { NSTAT = 16 };
 
 struct StepRec {
@@ -371,10 +371,145 @@ double path_length(const std::vector<V3>& f) {
 // Gradient of log p with respect to the vertices (declared below).
 void grad_vertices(const Ctx& cx, const Target& t, int n, const V3* f, V3* g);
 
+// ---------------------------------------------------------------------------
+// Proposals as functions of continuous draws.  The sampler below feeds them
+// the uniforms of its random words; the tests feed them arbitrary uniforms to
+// measure the density of each proposal from its own map (numerical Jacobian
+// of draws -> proposed path), independently of the printed J and q.
+// ---------------------------------------------------------------------------
+struct Prop {
+    int move;
+    std::vector<V3> y; // proposed path (empty: no proposal, rejected)
+    double logA;
+};
+
+// Three standard normals from four uniforms (Box-Muller, the fourth normal unused).
+V3 box_muller3(const double u[4]) {
+    double rho1 = std::sqrt(-2 * std::log(u[0]));
+    double rho2 = std::sqrt(-2 * std::log(u[2]));
+    return {rho1 * std::cos(2 * PI * u[1]), rho1 * std::sin(2 * PI * u[1]), rho2 * std::cos(2 * PI * u[3])};
+}
+
+// Step size of the single-vertex Langevin move at interior vertex j of f:
+// mala_h times the squared length of the shorter segment at f_j, so that the
+// drift and noise stay a fixed fraction of the local length scale.
+double local_h(const Params& P, const std::vector<V3>& f, int j) {
+    double la = norm(f[j] - f[j - 1]), lb = norm(f[j + 1] - f[j]);
+    double m = std::min(la, lb);
+    return P.mala_h * m * m;
+}
+
+// Perturbation of vertex j (1 <= j <= n-1) from the uniforms u[0..3]:
+//  - interior vertex, plain sampler: Gaussian step sigma * xi (symmetric);
+//  - interior vertex, single-vertex Langevin sampler: y_j = f_j + (h/2) g_j + sqrt(h) xi
+//    with g_j = d log p / d f_j and h = local_h, accepted with the ratio of the
+//    two Gaussian proposal densities (the reverse one at y);
+//  - the end point: von Mises-Fisher step on the sensor sphere about its
+//    current normal, cos = 1 + log(u0 + (1 - u0) e^{-2 kappa}) / kappa,
+//    azimuth 2 pi u1 (symmetric).
+Prop propose_perturb(const Ctx& cx, const Target& t, const Params& P, const std::vector<V3>& f, int j,
+                     const double u[4]) {
+    int n = (int)f.size();
+    Prop pr{MV_INTERIOR, f, NEG_INF};
+    if (j <= n - 2 && P.sampler == 2) {
+        pr.move = MV_LMALA;
+        std::vector<V3> gx(n), gy(n);
+        grad_vertices(cx, t, n, f.data(), gx.data());
+        double hx = local_h(P, f, j);
+        V3 xi = box_muller3(u);
+        pr.y[j] = f[j] + (0.5 * hx) * gx[j] + std::sqrt(hx) * xi;
+        double lpx = logp_path(cx, t, n, f.data()), lpy = logp_path(cx, t, n, pr.y.data());
+        if (std::isfinite(lpy)) {
+            grad_vertices(cx, t, n, pr.y.data(), gy.data());
+            double hy = local_h(P, pr.y, j);
+            V3 a = pr.y[j] - f[j] - (0.5 * hx) * gx[j];
+            V3 b = f[j] - pr.y[j] - (0.5 * hy) * gy[j];
+            // log N(y; x + hx/2 gx, hx) and log N(x; y + hy/2 gy, hy) in 3 dimensions
+            double lq_fwd = -1.5 * std::log(hx) - dot(a, a) / (2 * hx);
+            double lq_rev = -1.5 * std::log(hy) - dot(b, b) / (2 * hy);
+            pr.logA = lpy - lpx + lq_rev - lq_fwd;
+        }
+        return pr;
+    }
+    if (j <= n - 2) {
+        pr.y[j] = f[j] + P.sigma * box_muller3(u);
+    } else {
+        pr.move = MV_END;
+        V3 d = f[n - 1] - t.eta;
+        V3 nu = (1.0 / norm(d)) * d, e2, e3;
+        onb(nu, &e2, &e3);
+        double k = P.kappa_end;
+        double w = 1.0 + std::log(u[0] + (1.0 - u[0]) * std::exp(-2 * k)) / k;
+        double phi = 2 * PI * u[1];
+        double sw = std::sqrt(std::max(0.0, 1.0 - w * w));
+        V3 nn = w * nu + sw * (std::cos(phi) * e2 + std::sin(phi) * e3);
+        pr.y[n - 1] = t.eta + t.R * nn;
+    }
+    pr.logA = logp_path(cx, t, n, pr.y.data()) - logp_path(cx, t, n, f.data());
+    return pr;
+}
+
+// Metropolis-adjusted Langevin move of all interior vertices jointly:
+// y_k = f_k + (h/2) g_k + sqrt(h) xi_k, xi_k from the uniforms U[4(k-1) .. 4(k-1)+3].
+Prop propose_mala(const Ctx& cx, const Target& t, const Params& P, const std::vector<V3>& f, const double* U) {
+    int n = (int)f.size();
+    Prop pr{MV_MALA, f, NEG_INF};
+    double h = P.mala_h;
+    std::vector<V3> gx(n), gy(n);
+    grad_vertices(cx, t, n, f.data(), gx.data());
+    for (int k = 1; k <= n - 2; ++k) pr.y[k] = f[k] + (0.5 * h) * gx[k] + std::sqrt(h) * box_muller3(U + 4 * (k - 1));
+    double lpx = logp_path(cx, t, n, f.data()), lpy = logp_path(cx, t, n, pr.y.data());
+    if (std::isfinite(lpy)) {
+        grad_vertices(cx, t, n, pr.y.data(), gy.data());
+        double fwd = 0, rev = 0;
+        for (int k = 1; k <= n - 2; ++k) {
+            V3 a = pr.y[k] - f[k] - (0.5 * h) * gx[k];
+            V3 b = f[k] - pr.y[k] - (0.5 * h) * gy[k];
+            fwd += dot(a, a);
+            rev += dot(b, b);
+        }
+        pr.logA = lpy - lpx - rev / (2 * h) + fwd / (2 * h);
+    }
+    return pr;
+}
+
+// Birth of a vertex on segment k of f (n < cap) from the uniforms u[0..2]:
+// cos s by the inverse CDF of q(s), t = logit(u1) (logistic q(t)),
+// phi = 2 pi u2, new vertex at the bi-spherical point (s, t, phi) of the foci
+// f_k, f_{k+1}.
+Prop propose_birth(const Ctx& cx, const Target& t, const Params& P, const std::vector<V3>& f, int k,
+                   const double u[3]) {
+    Prop pr{MV_BIRTH, {}, NEG_INF};
+    double beta = centre_beta(cx, t, f[k], f[k + 1]);
+    double s = std::acos(std::max(-1.0, std::min(1.0, sample_cos_s(u[0], beta))));
+    double tt = std::log(u[1] / (1.0 - u[1]));
+    double phi = 2 * PI * u[2];
+    V3 fn = bisph(f[k], f[k + 1], s, tt, phi);
+    pr.y.assign(f.begin(), f.begin() + k + 1);
+    pr.y.push_back(fn);
+    pr.y.insert(pr.y.end(), f.begin() + k + 1, f.end());
+    pr.logA = log_birth_ratio(cx, t, P, f, k, pr.y, s, tt);
+    return pr;
+}
+
+// Death of interior vertex j of f (n > 2): the reverse of the birth that
+// would create f_j on the segment f_{j-1} f_{j+1} of the shorter path; its
+// ratio is the inverse of that birth's (alpha = min(1, 1/A)).
+Prop propose_death(const Ctx& cx, const Target& t, const Params& P, const std::vector<V3>& f, int j) {
+    Prop pr{MV_DEATH, f, NEG_INF};
+    pr.y.erase(pr.y.begin() + j);
+    double s, tt, phi;
+    bisph_inv(f[j - 1], f[j + 1], f[j], &s, &tt, &phi);
+    pr.logA = -log_birth_ratio(cx, t, P, pr.y, j - 1, f, s, tt);
+    return pr;
+}
+
 // One step of one chain: move selection from the schedule, proposal, Green
 // acceptance, update.  The random draws of the step are fixed by (seed,
 // chain, step): word 0 chooses the vertex/segment, word 1 is the accept
-// uniform, word 2 the birth/death coin, words 4..7 the proposal.
+// uniform, word 2 the birth/death coin, words 4..7 the proposal; the joint
+// Langevin move draws one more block per interior vertex k (counter word 3 =
+// 2 + k).
 StepRec rj_step(const Ctx& cx, const Target& t, const Params& P, uint32_t chain, uint64_t step,
                 std::vector<V3>& f) {
     uint32_t r[8];
@@ -382,70 +517,24 @@ StepRec rj_step(const Ctx& cx, const Target& t, const Params& P, uint32_t chain,
     StepRec rec{MV_NULL, 0, -1, NEG_INF, std::log(unif(r[1]))};
     int n = (int)f.size();
     bool perturb = (int)(step % (uint64_t)P.cycle_len) < P.n_perturb;
+    const double u4[4] = {unif(r[4]), unif(r[5]), unif(r[6]), unif(r[7])};
+    Prop pr{MV_NULL, {}, NEG_INF};
     if (perturb) {
         int j = 1 + (int)pick(r[0], (uint32_t)(n - 1));
         rec.index = j;
-        std::vector<V3> y = f;
         if (j <= n - 2 && P.sampler == 1) {
-            // Metropolis-adjusted Langevin move of all interior vertices.
-            rec.move = MV_MALA;
-            double h = P.mala_h;
-            std::vector<V3> gx(n), gy(n);
-            grad_vertices(cx, t, n, f.data(), gx.data());
-            double fwd = 0, rev = 0;
             uint32_t key[2] = {(uint32_t)P.seed, (uint32_t)(P.seed >> 32)};
-            std::vector<V3> xi(n);
+            std::vector<double> U(4 * (n - 2));
             for (int k = 1; k <= n - 2; ++k) {
                 uint32_t c[4] = {chain, (uint32_t)step, (uint32_t)(step >> 32), 2u + (uint32_t)k}, q[4];
                 philox4x32_10(c, key, q);
-                double rho1 = std::sqrt(-2 * std::log(unif(q[0])));
-                double rho2 = std::sqrt(-2 * std::log(unif(q[2])));
-                xi[k] = {rho1 * std::cos(2 * PI * unif(q[1])), rho1 * std::sin(2 * PI * unif(q[1])),
-                         rho2 * std::cos(2 * PI * unif(q[3]))};
-                y[k] = f[k] + (0.5 * h) * gx[k] + std::sqrt(h) * xi[k];
+                for (int i = 0; i < 4; ++i) U[4 * (k - 1) + i] = unif(q[i]);
             }
-            double lpx = logp_path(cx, t, n, f.data()), lpy = logp_path(cx, t, n, y.data());
-            if (std::isfinite(lpy)) {
-                grad_vertices(cx, t, n, y.data(), gy.data());
-                for (int k = 1; k <= n - 2; ++k) {
-                    V3 a = y[k] - f[k] - (0.5 * h) * gx[k];
-                    V3 b = f[k] - y[k] - (0.5 * h) * gy[k];
-                    fwd += dot(a, a);
-                    rev += dot(b, b);
-                }
-                rec.logA = lpy - lpx - rev / (2 * h) + fwd / (2 * h);
-            }
-        } else if (j <= n - 2) {
-            // Gaussian step of one interior vertex (symmetric).
-            rec.move = MV_INTERIOR;
-            double rho1 = std::sqrt(-2 * std::log(unif(r[4])));
-            double rho2 = std::sqrt(-2 * std::log(unif(r[6])));
-            V3 xi = {rho1 * std::cos(2 * PI * unif(r[5])), rho1 * std::sin(2 * PI * unif(r[5])),
-                     rho2 * std::cos(2 * PI * unif(r[7]))};
-            y[j] = f[j] + P.sigma * xi;
-            rec.logA = logp_path(cx, t, n, y.data()) - logp_path(cx, t, n, f.data());
+            pr = propose_mala(cx, t, P, f, U.data());
         } else {
-            // von Mises-Fisher step of the end point on the sensor surface (symmetric).
-            rec.move = MV_END;
-            V3 d = f[n - 1] - t.eta;
-            V3 nu = (1.0 / norm(d)) * d, e2, e3;
-            onb(nu, &e2, &e3);
-            double k = P.kappa_end, u = unif(r[4]);
-            double w = 1.0 + std::log(u + (1.0 - u) * std::exp(-2 * k)) / k;
-            double phi = 2 * PI * unif(r[5]);
-            double sw = std::sqrt(std::max(0.0, 1.0 - w * w));
-            V3 nn = w * nu + sw * (std::cos(phi) * e2 + std::sin(phi) * e3);
-            y[n - 1] = t.eta + t.R * nn;
-            rec.logA = logp_path(cx, t, n, y.data()) - logp_path(cx, t, n, f.data());
+            pr = propose_perturb(cx, t, P, f, j, u4);
         }
-        if (rec.logu < rec.logA) {
-            rec.accepted = 1;
-            f = y;
-        }
-        return rec;
-    }
-    bool birth = r[2] < P.birth_thresh;
-    if (birth) {
+    } else if (r[2] < P.birth_thresh) {
         rec.move = MV_BIRTH;
         if (n >= cx.cap) return rec; // p(n > cap) = 0 (reading R9)
         double S = 0;
@@ -460,34 +549,19 @@ StepRec rj_step(const Ctx& cx, const Target& t, const Params& P, uint32_t chain,
             if (cum > target) { k = l; break; }
         }
         rec.index = k;
-        double beta = centre_beta(cx, t, f[k], f[k + 1]);
-        double s = std::acos(std::max(-1.0, std::min(1.0, sample_cos_s(unif(r[4]), beta))));
-        double u5 = unif(r[5]);
-        double tt = std::log(u5 / (1.0 - u5));
-        double phi = 2 * PI * unif(r[6]);
-        V3 fn = bisph(f[k], f[k + 1], s, tt, phi);
-        std::vector<V3> y(f.begin(), f.begin() + k + 1);
-        y.push_back(fn);
-        y.insert(y.end(), f.begin() + k + 1, f.end());
-        rec.logA = log_birth_ratio(cx, t, P, f, k, y, s, tt);
-        if (rec.logu < rec.logA) {
-            rec.accepted = 1;
-            f = y;
-        }
-        return rec;
+        pr = propose_birth(cx, t, P, f, k, u4);
+    } else {
+        rec.move = MV_DEATH;
+        if (n <= 2) return rec; // no intermediate vertex to remove (reading R9)
+        int j = 1 + (int)pick(r[0], (uint32_t)(n - 2));
+        rec.index = j;
+        pr = propose_death(cx, t, P, f, j);
     }
-    rec.move = MV_DEATH;
-    if (n <= 2) return rec; // no intermediate vertex to remove (reading R9)
-    int j = 1 + (int)pick(r[0], (uint32_t)(n - 2));
-    rec.index = j;
-    std::vector<V3> x(f);
-    x.erase(x.begin() + j);
-    double s, tt, phi;
-    bisph_inv(f[j - 1], f[j + 1], f[j], &s, &tt, &phi);
-    rec.logA = -log_birth_ratio(cx, t, P, x, j - 1, f, s, tt); // alpha = min(1, 1/A)
+    rec.move = pr.move;
+    rec.logA = pr.logA;
     if (rec.logu < rec.logA) {
         rec.accepted = 1;
-        f = x;
+        f = pr.y;
     }
     return rec;
 }
@@ -501,12 +575,12 @@ void accumulate(const Ctx& cx, const Target& t, const std::vector<V3>& f, const 
     st[3] += L;
     st[4] += L * L;
     st[5] += n;
-    int cls = (rec.move == MV_INTERIOR || rec.move == MV_END || rec.move == MV_MALA) ? 0
+    int cls = (rec.move == MV_INTERIOR || rec.move == MV_END || rec.move == MV_MALA || rec.move == MV_LMALA) ? 0
               : (rec.move == MV_BIRTH ? 1 : 2);
     st[6 + cls] += 1;
     st[9 + cls] += rec.accepted;
     st[12] += (n == cx.cap);
-    if (rec.move == MV_MALA) {
+    if (rec.move == MV_MALA || rec.move == MV_LMALA) {
         st[13] += 1;
         st[14] += rec.accepted;
     }
@@ -838,16 +912,27 @@ double solve_flight(const Medium& m, double u0, double du, double taub) {
 }
 
 const int NBUCKET = 8; // detected weight split by number of scatterings (last: >= 7)
+const int NLBIN = 48;  // detected weight split by path length (bins of a given width; last: overflow)
+// Per-photon tallies of the tracer, each summed over photons with its square:
+//  [0] detected weight; [1 + b] weight after b scatterings; [9 + b] weight x
+//  path length after b scatterings; [17] weight x path length; [18] weight x
+//  number of scatterings; [19 + i] weight with path length in bin i.
+const int NTALLY = 19 + NLBIN;
 
-double trace_photons(const Ctx& cx, const Target& t, uint64_t seed, uint32_t stream, int64_t nphot, double esc,
-                     double* sum2_out, double* bucket, double* bucket2) {
+// Every sensor entry is scored with the photon's weight and the path length
+// L travelled up to the entry point (the photon's arrival time is L over the
+// speed of light).  For a homogeneous medium the weight of a detected path is
+// e^{-a L}, and the flights are drawn from b e^{-b l}, so the derivatives of
+// the detected intensity are the tallies dI/da = -E[w L] and
+// dI/db = E[w (N/b - L)] (N scatterings).
+void trace_photons(const Ctx& cx, const Target& t, uint64_t seed, uint32_t stream, int64_t nphot, double esc,
+                   double lbin, double* S, double* S2) {
     const Medium& m = cx.media[t.medium];
     Rng g{seed, stream, 0, {0, 0, 0, 0}, 4};
-    double sum = 0, sum2 = 0;
     V3 srcu = {0, 0, 0};
     for (int64_t p = 0; p < nphot; ++p) {
         V3 x = srcu, n = sample_emission(t, g);
-        double lw = 0.0, score = 0.0, sb[NBUCKET] = {0};
+        double lw = 0.0, Lp = 0.0, T[NTALLY] = {0};
         int nsc = 0;
         for (int it = 0; it < 1000000; ++it) {
             double taub = -std::log(g.next());
@@ -862,13 +947,20 @@ double trace_photons(const Ctx& cx, const Target& t, uint64_t seed, uint32_t str
                     V3 hit = x + d * n;
                     double ta = depth(m, m.a, uX, axis_coord(cx, t, hit), d);
                     double sc = std::exp(lw - ta) * detection(t, (1.0 / t.R) * (hit - t.eta));
-                    score += sc;
-                    sb[std::min(nsc, NBUCKET - 1)] += sc;
+                    double Lh = Lp + d;
+                    int bk = std::min(nsc, NBUCKET - 1);
+                    T[0] += sc;
+                    T[1 + bk] += sc;
+                    T[9 + bk] += sc * Lh;
+                    T[17] += sc * Lh;
+                    T[18] += sc * nsc;
+                    if (lbin > 0) T[19 + (int)std::min((double)(NLBIN - 1), std::floor(Lh / lbin))] += sc;
                 }
             }
             if (!std::isfinite(dL)) break;
             V3 xn = x + dL * n;
             lw -= depth(m, m.a, uX, axis_coord(cx, t, xn), dL);
+            Lp += dL;
             x = xn;
             if (norm(x - t.eta) > esc) break;
             if (lw < std::log(1e-4)) { // Russian roulette
@@ -880,15 +972,11 @@ double trace_photons(const Ctx& cx, const Target& t, uint64_t seed, uint32_t str
             n = rotate_dir(n, c, 2 * PI * g.next());
             ++nsc;
         }
-        sum += score;
-        sum2 += score * score;
-        for (int b = 0; b < NBUCKET; ++b) {
-            bucket[b] += sb[b];
-            bucket2[b] += sb[b] * sb[b];
+        for (int k = 0; k < NTALLY; ++k) {
+            S[k] += T[k];
+            S2[k] += T[k] * T[k];
         }
     }
-    *sum2_out = sum2;
-    return sum;
 }
 
 } // namespace
@@ -1014,6 +1102,30 @@ void orc_step(void* h, const uint64_t* ip, const double* dp, uint32_t chain, int
     rec[4] = r.logu;
 }
 
+// One proposal from continuous draws (tests of the proposal densities).
+// kind: 0 perturbation of vertex idx (u: 4 uniforms), 1 birth on segment idx
+// (u: 3 uniforms), 2 death of vertex idx, 3 joint Langevin move (u: 4 uniforms
+// per interior vertex).  y: room for n + 1 vertices; *ny receives the
+// proposal's vertex count (0: no proposal).  Returns log A.
+double orc_propose(void* h, const uint64_t* ip, const double* dp, int t, int kind, int n, const double* v, int idx,
+                   const double* u, int* ny, double* y, int* move) {
+    Ctx* cx = (Ctx*)h;
+    Params P{ip[0], ip[1], (int64_t)ip[2], (int)ip[3], (int)ip[4], (int)ip[5], (uint32_t)ip[6], dp[0], dp[1],
+             (int)ip[7], dp[2]};
+    const Target& tg = cx->targets[t];
+    std::vector<V3> f(n);
+    for (int k = 0; k < n; ++k) f[k] = ld3(v + 3 * k);
+    Prop pr{MV_NULL, {}, NEG_INF};
+    if (kind == 0) pr = propose_perturb(*cx, tg, P, f, idx, u);
+    else if (kind == 1) pr = propose_birth(*cx, tg, P, f, idx, u);
+    else if (kind == 2) pr = propose_death(*cx, tg, P, f, idx);
+    else pr = propose_mala(*cx, tg, P, f, u);
+    *ny = (int)pr.y.size();
+    for (int k = 0; k < *ny; ++k) st3(y + 3 * k, pr.y[k]);
+    *move = pr.move;
+    return pr.logA;
+}
+
 // Run `steps` steps for chains [0, C): per-chain state in/out, per-chain
 // statistics added into stats (C * 16).  Chains are split over threads.
 // trace (optional): C * steps * 5 doubles, record of every step.
@@ -1064,35 +1176,35 @@ double orc_anchor_I3(void* h, int t, int nth, int nps, int nr, int nv, int npsi)
     return anchor_I3(*cx, cx->targets[t], nth, nps, nr, nv, npsi);
 }
 
-// Analog tracer: mean detected weight per photon and its standard error
-// (mean_se[0..1]), then the same split by number of scatterings
-// (mean_se[2 + 2b], mean_se[3 + 2b], b = 0..7; bucket 7 collects >= 7).
-// nphot photons split over nthreads independent streams.
-void orc_trace(void* h, int t, uint64_t seed, int64_t nphot, double esc, int nthreads, double* mean_se) {
+// Analog tracer: per-photon mean and standard error of every tally
+// (mean_se[2k], mean_se[2k + 1] for tally k = 0 .. NTALLY-1, see
+// trace_photons).  nphot photons split over nthreads independent streams;
+// lbin: path-length bin width of the length tallies (0: none).
+void orc_trace(void* h, int t, uint64_t seed, int64_t nphot, double esc, double lbin, int nthreads,
+               double* mean_se) {
     Ctx* cx = (Ctx*)h;
-    std::vector<double> s(nthreads, 0), s2(nthreads, 0), b(nthreads * NBUCKET, 0), b2(nthreads * NBUCKET, 0);
+    std::vector<double> S((size_t)nthreads * NTALLY, 0), S2((size_t)nthreads * NTALLY, 0);
     std::vector<std::thread> th;
     for (int i = 0; i < nthreads; ++i) {
         int64_t cnt = nphot / nthreads + (i < nphot % nthreads ? 1 : 0);
         th.emplace_back([&, i, cnt]() {
-            s[i] = trace_photons(*cx, cx->targets[t], seed, (uint32_t)i, cnt, esc, &s2[i], &b[i * NBUCKET],
-                                 &b2[i * NBUCKET]);
+            trace_photons(*cx, cx->targets[t], seed, (uint32_t)i, cnt, esc, lbin, &S[(size_t)i * NTALLY],
+                          &S2[(size_t)i * NTALLY]);
         });
     }
     for (auto& x : th) x.join();
-    auto fin = [&](double S, double S2, double* out) {
-        double mean = S / nphot;
-        out[0] = mean;
-        out[1] = std::sqrt(std::max(0.0, S2 / nphot - mean * mean) / nphot);
-    };
-    double S = 0, S2 = 0;
-    for (int i = 0; i < nthreads; ++i) { S += s[i]; S2 += s2[i]; }
-    fin(S, S2, mean_se);
-    for (int k = 0; k < NBUCKET; ++k) {
-        double B = 0, B2 = 0;
-        for (int i = 0; i < nthreads; ++i) { B += b[i * NBUCKET + k]; B2 += b2[i * NBUCKET + k]; }
-        fin(B, B2, mean_se + 2 + 2 * k);
+    for (int k = 0; k < NTALLY; ++k) {
+        double A = 0, A2 = 0;
+        for (int i = 0; i < nthreads; ++i) {
+            A += S[(size_t)i * NTALLY + k];
+            A2 += S2[(size_t)i * NTALLY + k];
+        }
+        double mean = A / nphot;
+        mean_se[2 * k] = mean;
+        mean_se[2 * k + 1] = std::sqrt(std::max(0.0, A2 / nphot - mean * mean) / nphot);
     }
 }
+
+int orc_trace_tallies(void) { return NTALLY; }
 
 } // extern "C"
