@@ -157,8 +157,8 @@ typedef struct {
  * tables, else RJPATH_EINVAL) select the launch; 0 takes the values tuned for
  * this handle (see rjpath_autotune) or a default.  chunk: steps per kernel launch (0 = all).
  * trace: NULL or n_chains * steps * RJPATH_TRACE_WORDS doubles.
- * hist: NULL or n_targets * (cap + 1) uint32 counts of the sector n after
- * every post-burn-in step (for tuning the sector tilt).
+ * hist: NULL or n_targets * (cap + 1) uint32 counts (added to) of the sector n
+ * after every step of the call, burn-in included (for tuning the sector tilt).
  * step_counter: NULL, or a device uint64 holding the global step index; the
  * kernels then read the first step from it (step0 is ignored) and the call
  * enqueues an increment by `steps` after them.  A captured graph of the call
@@ -249,9 +249,34 @@ int rjpath_intensity(rjpath_medium* m, const rjpath_targets* t, const rjpath_cha
 int rjpath_grad(rjpath_medium* m, const rjpath_targets* t, const rjpath_chains* c, double* logp_out,
                 void* dlogp_dv, double* score, void* stream);
 
+/* Sector-tilt tuning (the tilt w(n) of the anchored estimator; the estimator
+ * undoes it, so any tilt leaves the intensity unchanged, but a flat sector
+ * histogram lets distant targets visit the anchor sector n0 often).
+ * Runs `rounds` pilot rounds of p->steps sampler steps each, starting at
+ * p->step0 (ordinary steps: the chains advance by rounds * p->steps steps;
+ * the per-chain statistics are left untouched).  After each round, for every
+ * target, log w(n) is raised by log(h(mode) / h(n)) for n0 <= n < mode, where
+ * h is that round's sector histogram and mode its most visited sector (by
+ * floor_push where h(n) = 0), and clamped to [0, max_logw].
+ * t->logw: device, n_targets * (cap + 1) doubles, updated in place (required).
+ * hist: device workspace of n_targets * (cap + 1) uint32; holds the last
+ * round's histogram on return.  p->step_counter and p->trace must be NULL.
+ * Asynchronous on `stream`; allocates nothing. */
+int rjpath_tune_tilt(rjpath_medium* m, const rjpath_targets* t, const rjpath_chains* c, const rjpath_run_params* p,
+                     int32_t rounds, uint32_t* hist, double max_logw, double floor_push, void* stream);
+
+/* d log I_t / d theta from the score sums of rjpath_grad (the score identity
+ * of the path integral, App. "Path probability distribution"):
+ * dlogI[t][3 l + k] = score[t][1 + 3 l + k] / score[t][0] for the global layer
+ * index l and theta = (lambda_s, lambda_a, g); NaN for a target without
+ * samples.  score: device, n_targets * (1 + 3 L_total) doubles; dlogI: device,
+ * n_targets * 3 L_total doubles.  Asynchronous on `stream`. */
+int rjpath_dlogi_dtheta(rjpath_medium* m, const rjpath_targets* t, const double* score, double* dlogI, void* stream);
+
 /* Times short launches of rjpath_run_chains over the candidate launch
- * configurations (chains per block in {64, 128, 256} x LDS vertex slots in
- * {4, 8, 12, 16, 24, 32, 48, 64}, capped at cap and at 160 KiB of LDS) on the
+ * configurations (the default launch, and chains per block in {64, 256} x
+ * LDS vertex slots in {8, 12, 16, 24, 32}, capped at cap and at 160 KiB of
+ * LDS; at most 11) on the
  * given chains, advancing them by exactly `steps` steps starting at p->step0
  * (ordinary sampler steps, so they may serve as burn-in: the chain trajectory
  * does not depend on the launch configuration), and stores the fastest

@@ -54,7 +54,7 @@ def lib():
             "orc_tau": (d, [p, i, p, p, i]),
             "orc_beta": (d, [p, i, p, p]),
             "orc_grad": (None, [p, i, i, p, p, p, p, p]),
-            "orc_step": (None, [p, p, p, u32, i, p, p, p]),
+            "orc_step": (None, [p, p, p, u32, i, p, p, p, p, p]),
             "orc_propose": (d, [p, p, p, i, i, i, p, i, p, p, p, p]),
             "orc_run": (None, [p, p, p, i, p, p, p, p, p, p, i]),
             "orc_anchor_I2": (d, [p, i, i, i]),
@@ -214,15 +214,22 @@ class Oracle:
         dp = np.array([run["sigma"], run["kappa_end"], run.get("mala_h", 0.05)], np.float64)
         return ip, dp
 
-    def step(self, run, chain, t, n, verts, step):
-        """One step of one chain; returns (n, verts, record)."""
+    def step(self, run, chain, t, n, verts, step, proposal=False):
+        """One step of one chain; returns (n, verts, record) and, if asked,
+        the proposed path (None when the step made no proposal)."""
         ip, dp = self._params(run, step, 1)
         v = np.zeros((self.cap, 3))
         v[:n] = np.asarray(verts)[:n]
         nn = C.c_int(int(n))
         rec = np.zeros(5)
-        lib().orc_step(self.h, _ptr(ip), _ptr(dp), int(chain), int(t), C.byref(nn), _ptr(v), _ptr(rec))
-        return nn.value, v[: nn.value].copy(), rec
+        npr = C.c_int(0)
+        pr = np.zeros((self.cap + 1, 3)) if proposal else None
+        lib().orc_step(self.h, _ptr(ip), _ptr(dp), int(chain), int(t), C.byref(nn), _ptr(v), _ptr(rec),
+                       C.byref(npr), _ptr(pr))
+        out = (nn.value, v[: nn.value].copy(), rec)
+        if proposal:
+            return out + ((pr[: npr.value].copy() if npr.value else None),)
+        return out
 
     def propose(self, run, t, verts, kind, idx, u):
         """One proposal from continuous draws u (see orc_propose): returns

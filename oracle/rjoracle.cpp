@@ -511,7 +511,7 @@ Prop propose_death(const Ctx& cx, const Target& t, const Params& P, const std::v
 // Langevin move draws one more block per interior vertex k (counter word 3 =
 // 2 + k).
 StepRec rj_step(const Ctx& cx, const Target& t, const Params& P, uint32_t chain, uint64_t step,
-                std::vector<V3>& f) {
+                std::vector<V3>& f, std::vector<V3>* proposal = nullptr) {
     uint32_t r[8];
     step_draws(P.seed, chain, step, r);
     StepRec rec{MV_NULL, 0, -1, NEG_INF, std::log(unif(r[1]))};
@@ -559,6 +559,7 @@ StepRec rj_step(const Ctx& cx, const Target& t, const Params& P, uint32_t chain,
     }
     rec.move = pr.move;
     rec.logA = pr.logA;
+    if (proposal) *proposal = pr.y;
     if (rec.logu < rec.logA) {
         rec.accepted = 1;
         f = pr.y;
@@ -1085,14 +1086,21 @@ void orc_grad(void* h, int t, int n, const double* v, double* gv, double* d_lams
 
 // One step of one chain (for lock-step replay against the device).
 // v: 3*cap doubles (in/out), n in/out.  rec: move, accepted, index, logA, logu.
+// prop (optional, 3*(cap+1) doubles) receives the proposed path, *nprop its
+// vertex count (0 when the step made no proposal).
 void orc_step(void* h, const uint64_t* ip, const double* dp, uint32_t chain, int t, int* n, double* v,
-              double* rec) {
+              double* rec, int* nprop, double* prop) {
     Ctx* cx = (Ctx*)h;
     Params P{ip[0], ip[1], (int64_t)ip[2], (int)ip[3], (int)ip[4], (int)ip[5], (uint32_t)ip[6], dp[0], dp[1],
              (int)ip[7], dp[2]};
     std::vector<V3> f(*n);
     for (int k = 0; k < *n; ++k) f[k] = ld3(v + 3 * k);
-    StepRec r = rj_step(*cx, cx->targets[t], P, chain, P.step0, f);
+    std::vector<V3> y;
+    StepRec r = rj_step(*cx, cx->targets[t], P, chain, P.step0, f, prop ? &y : nullptr);
+    if (prop) {
+        *nprop = (int)y.size();
+        for (int k = 0; k < *nprop; ++k) st3(prop + 3 * k, y[k]);
+    }
     *n = (int)f.size();
     for (int k = 0; k < *n; ++k) st3(v + 3 * k, f[k]);
     rec[0] = r.move;

@@ -38,7 +38,9 @@ int exercise(void* h, int cap, int n_targets, double D) {
         orc_run(h, ip, dp, C, ids.data(), tgt.data(), n.data(), v.data(), stats.data(), trace.data(), 2);
         int nn = n[0];
         double rec[5];
-        orc_step(h, ip, dp, 0, tgt[0], &nn, v.data(), rec);
+        int np_ = 0;
+        std::vector<double> prop((size_t)(cap + 1) * 3);
+        orc_step(h, ip, dp, 0, tgt[0], &nn, v.data(), rec, &np_, prop.data());
     }
     // proposals from continuous draws
     uint64_t ip[8] = {7, 0, 0, 1, 5, 3, 1u << 31, 2};

@@ -19,7 +19,9 @@ from . import tune as tuning
 def run_intensity_and_score(w, theta, chunks=4, chunk_steps=500, burn_in=500, tilt=True, precision="f32",
                             device="cuda", anchor=None, groups=16):
     """Samples the workload under theta ((L, 3): lambda_s, lambda_a, g) and
-    returns (I, se, dlogI (T, L, 3), sampler)."""
+    returns (I, se, dlogI (T, L, 3), sampler).  The score sums accumulate on
+    the device across the chunks (rjpath_grad) and rjpath_dlogi_dtheta forms the
+    ratio; this function only sequences the calls."""
     th = theta.detach().to("cpu", torch.float64).numpy()
     ww = dict(w)
     ww["lam_s"], ww["lam_a"], ww["g"] = th[:, 0].copy(), th[:, 1].copy(), th[:, 2].copy()
@@ -29,17 +31,14 @@ def run_intensity_and_score(w, theta, chunks=4, chunk_steps=500, burn_in=500, ti
         tuning.tune_tilt(s)
     s.run(burn_in)
     s.stats.zero_()
-    score = None
+    score = torch.zeros((s.T, 1 + 3 * s.medium.L_total), dtype=torch.float64, device=s.dev)
     for _ in range(chunks):
         s.run(chunk_steps)
-        _, _, sc = s.grad(logp=False, score=True)
-        score = sc if score is None else score + sc
+        s.grad(logp=False, score=score)
     if anchor is not None:
         s._anchor = np.asarray(anchor, np.float64)
     res = s.intensity(groups=groups)
-    L = th.shape[0]
-    sc = score.cpu().numpy()
-    dlogI = sc[:, 1:].reshape(-1, L, 3) / np.maximum(sc[:, :1, None], 1e-300)
+    dlogI = s.dlogI(score).cpu().numpy()
     return res["I"], res["se"], dlogI, s
 
 
@@ -54,6 +53,7 @@ class RJPathIntensity(torch.autograd.Function):
         It = torch.as_tensor(I, dtype=torch.float64)
         ctx.save_for_backward(It, torch.as_tensor(dlogI, dtype=torch.float64))
         ctx.se = se
+        ctx.theta_device, ctx.theta_dtype = theta.device, theta.dtype
         return It.to(theta.device)
 
     @staticmethod
@@ -61,4 +61,4 @@ class RJPathIntensity(torch.autograd.Function):
         I, dlogI = ctx.saved_tensors
         g = gI.detach().to("cpu", torch.float64)
         grad = (g[:, None, None] * I[:, None, None] * dlogI).sum(0)
-        return grad, None, None
+        return grad.to(ctx.theta_device, ctx.theta_dtype), None, None

@@ -1,5 +1,4 @@
-// rj_anchor.hip -- the anchor-sector integrals of the intensity estimator
-// and the per-target reduction of the chain statistics.
+// rj_anchor.hip -- the anchor-sector integrals of the intensity estimator.
 //
 // The chains sample p(f) w(n) up to its normalisation; the integral of p over
 // one sector n0 is computed here by deterministic quadrature, so that
@@ -191,43 +190,11 @@ __global__ void __launch_bounds__(256) anchor_kernel(KArgs a, const double* gx, 
     if (threadIdx.x == 0) anchor[t] = red[0];
 }
 
-__device__ __forceinline__ uint32_t mix32(uint32_t x) {
-    // integer finaliser (MurmurHash3 fmix32) for interleaved chain groups
-    x ^= x >> 16;
-    x *= 0x85ebca6bu;
-    x ^= x >> 13;
-    x *= 0xc2b2ae35u;
-    x ^= x >> 16;
-    return x;
-}
-
-__global__ void __launch_bounds__(256) reduce_kernel(KArgs a, int groups, double* red) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= a.C || a.status[c] != 0) return;
-    const int t = a.target[c];
-    if (t < 0 || t >= a.T) return;
-    const int g = (int)(mix32((uint32_t)c) % (uint32_t)groups);
-    const double* s = a.stats + (size_t)c * RJPATH_NSTAT;
-    double* r = red + ((size_t)t * groups + g) * RD_NW;
-    atomicAdd(r + RD_SAMPLES, s[0]);
-    atomicAdd(r + RD_A, s[1]);
-    atomicAdd(r + RD_B, s[2]);
-    atomicAdd(r + RD_L, s[3]);
-    atomicAdd(r + RD_L2, s[4]);
-    atomicAdd(r + RD_CHAINS, 1.0);
-}
-
 } // namespace
 
 hipError_t launch_anchor(const KArgs& a, const double* gl_x, const double* gl_w, int ngl, double* anchor,
                          hipStream_t s) {
     hipLaunchKernelGGL(anchor_kernel, dim3(a.T), dim3(256), 0, s, a, gl_x, gl_w, ngl, anchor);
-    return hipGetLastError();
-}
-
-hipError_t launch_reduce(const KArgs& a, int groups, double* red, hipStream_t s) {
-    int block = 256, grid = (a.C + block - 1) / block;
-    hipLaunchKernelGGL(reduce_kernel, dim3(grid), dim3(block), 0, s, a, groups, red);
     return hipGetLastError();
 }
 

@@ -431,8 +431,14 @@ int rjpath_autotune(rjpath_medium* m, const rjpath_targets* t, const rjpath_chai
     hipStream_t s = (hipStream_t)stream;
     std::vector<std::pair<int, int>> cand;
     const size_t budget = slot_budget(m, t, c);
-    for (int b : {64, 128, 256})
-        for (int v : {4, 8, 12, 16, 24, 32, 48, 64}) {
+    {
+        // the default launch is always a candidate
+        int db, dv;
+        default_launch(c, make_args(m, t, c).tab_bytes, db, dv);
+        if ((size_t)(dv + 2) * db * vtx_bytes(c->precision) <= budget) cand.push_back({db, dv});
+    }
+    for (int b : {64, 256})
+        for (int v : {8, 12, 16, 24, 32}) {
             int vv = std::min(v, c->cap);
             if ((size_t)(vv + 2) * b * vtx_bytes(c->precision) > budget) continue;
             if (std::find(cand.begin(), cand.end(), std::make_pair(b, vv)) == cand.end()) cand.push_back({b, vv});
@@ -493,6 +499,41 @@ int rjpath_grad(rjpath_medium* m, const rjpath_targets* t, const rjpath_chains* 
     return RJPATH_OK;
 }
 
+int rjpath_tune_tilt(rjpath_medium* m, const rjpath_targets* t, const rjpath_chains* c, const rjpath_run_params* p,
+                     int32_t rounds, uint32_t* hist, double max_logw, double floor_push, void* stream) {
+    int r = check_run(m, t, c, p);
+    if (r) return r;
+    if (!t->logw) return fail(RJPATH_EINVAL, "rjpath_tune_tilt needs the targets' logw table (updated in place)");
+    if (!hist) return fail(RJPATH_EINVAL, "null histogram workspace");
+    if (rounds < 1 || p->steps < 1) return fail(RJPATH_EINVAL, "rounds and steps must be >= 1");
+    if (p->step_counter || p->trace) return fail(RJPATH_EINVAL, "rjpath_tune_tilt takes a host step0 and no trace");
+    if (!(max_logw >= 0) || !(floor_push >= 0)) return fail(RJPATH_EINVAL, "max_logw and floor_push must be >= 0");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t nh = (size_t)t->n_targets * (c->cap + 1);
+    rjpath_run_params q = *p;
+    q.hist = hist;
+    q.chunk = 0;
+    for (int i = 0; i < rounds; ++i) {
+        q.step0 = p->step0 + (uint64_t)i * p->steps;
+        // pilot steps leave the chain statistics untouched
+        q.burn_in = (int64_t)(q.step0 + p->steps);
+        HIPCHK(fill_u32(hist, nh, 0u, s), "fill kernel launch");
+        r = rjpath_run_chains(m, t, c, &q, stream);
+        if (r) return r;
+        HIPCHK(launch_tilt(t->n_targets, c->cap, t->n0, hist, (double*)t->logw, max_logw, floor_push, s),
+               "tilt kernel launch");
+    }
+    return RJPATH_OK;
+}
+
+int rjpath_dlogi_dtheta(rjpath_medium* m, const rjpath_targets* t, const double* score, double* dlogI, void* stream) {
+    int r = check_targets(m, t);
+    if (r) return r;
+    if (!score || !dlogI) return fail(RJPATH_EINVAL, "null score or dlogI");
+    HIPCHK(launch_dlogi(t->n_targets, 3 * m->L_total, score, dlogI, (hipStream_t)stream), "dlogI kernel launch");
+    return RJPATH_OK;
+}
+
 int rjpath_anchor(rjpath_medium* m, const rjpath_targets* t, double* anchor, void* stream) {
     if (!anchor) return fail(RJPATH_EINVAL, "null anchor output");
     int r = check_targets(m, t);
@@ -527,7 +568,7 @@ int rjpath_intensity(rjpath_medium* m, const rjpath_targets* t, const rjpath_cha
     if (r) return r;
     double* d_red = m->d_ws;
     KArgs a = make_args(m, t, c);
-    HIPCHK(hipMemsetAsync(d_red, 0, sizeof(double) * nred, s), "hipMemsetAsync");
+    HIPCHK(fill_f64(d_red, nred, 0.0, s), "fill kernel launch");
     HIPCHK(launch_reduce(a, groups, d_red, s), "reduce kernel launch");
     std::vector<double> red(nred);
     HIPCHK(hipMemcpyAsync(red.data(), d_red, sizeof(double) * nred, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");

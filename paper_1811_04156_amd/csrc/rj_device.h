@@ -103,7 +103,8 @@ template <class R> __device__ __forceinline__ LayV<R> lay_load(const R* p) {
 // Per-chain view of its target: sensor, emission, detection and medium.
 // ---------------------------------------------------------------------------
 template <class R> struct Tgt {
-    V3<R> eta;    // sensor centre relative to the source
+    V3<R> eta;    // sensor centre relative to the source (rounded to R)
+    V3<R> eta_lo; // its rounding error: eta + eta_lo is the FP64 value
     R rad;        // sensor radius
     int ek;       // emission kind
     V3<R> ed;     // emission axis
@@ -122,6 +123,14 @@ template <class R> struct Tgt {
     const double* edge;  // edges of this medium (mcnt + 1)
     const double2* pre;  // prefix integrals (c, b) at the edges
 };
+
+// p - eta for a point p near the sensor: p - eta_hi is exact there (the two
+// are within a factor of two of each other), so the offset from the sensor
+// centre keeps its full relative precision although both lie ~100 m from the
+// source where the coordinates are kept.
+template <class R> __device__ __forceinline__ V3<R> from_eta(const Tgt<R>& T, V3<R> p) {
+    return (p - T.eta) - T.eta_lo;
+}
 
 template <class R> __device__ __forceinline__ LayV<R> lay_at(const Tgt<R>& T, int l) {
     if (T.mcnt == 1) return T.l0;
@@ -230,7 +239,7 @@ template <class R> __device__ __forceinline__ R emit_term(const Tgt<R>& T, V3<R>
 // log of the final factor without its segment terms: log max(0, -u . nu) +
 // log rho(nu), with nu the outward normal at the end point fe.
 template <class R> __device__ __forceinline__ R end_term(const Tgt<R>& T, V3<R> ul, V3<R> fe) {
-    V3<R> d = fe - T.eta;
+    V3<R> d = from_eta(T, fe);
     V3<R> nu = Mth<R>::rsqrt(dot(d, d)) * d;
     R c = -dot(ul, nu);
     if (!(c > (R)0)) return Mth<R>::ninf();
@@ -272,6 +281,12 @@ template <class R> __device__ __forceinline__ V3<R> unit_dir(V3<R> P, V3<R> Q) {
     return Mth<R>::rsqrt(dot(r, r)) * r;
 }
 
+// unit vector from the sensor centre to Q
+template <class R> __device__ __forceinline__ V3<R> unit_dir_eta(const Tgt<R>& T, V3<R> Q) {
+    V3<R> r = from_eta(T, Q);
+    return Mth<R>::rsqrt(dot(r, r)) * r;
+}
+
 // Orthonormal completion of a unit vector (Duff et al., JCGT 2017).
 template <class R> __device__ __forceinline__ void onb(V3<R> n, V3<R>& e2, V3<R>& e3) {
     R sgn = copysign((R)1, n.z);
@@ -294,7 +309,9 @@ template <class R>
 __device__ __forceinline__ void load_target(const KArgs& a, int t, Tgt<R>& T, const MedTab<R>& tab) {
     const double* s = a.sensor + 3 * t;
     const double* o = a.src + 3 * t;
-    T.eta = {(R)(s[0] - o[0]), (R)(s[1] - o[1]), (R)(s[2] - o[2])};
+    const double ex = s[0] - o[0], ey = s[1] - o[1], ez = s[2] - o[2];
+    T.eta = {(R)ex, (R)ey, (R)ez};
+    T.eta_lo = {(R)(ex - (double)T.eta.x), (R)(ey - (double)T.eta.y), (R)(ez - (double)T.eta.z)};
     T.rad = (R)a.radius[t];
     T.ek = a.ek[t];
     T.ed = {(R)a.edir[3 * t], (R)a.edir[3 * t + 1], (R)a.edir[3 * t + 2]};

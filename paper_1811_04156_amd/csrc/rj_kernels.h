@@ -32,5 +32,13 @@ hipError_t launch_anchor(const KArgs& a, const double* gl_x, const double* gl_w,
                          hipStream_t s);
 // per (target, group) sums of the chain statistics into red[T * groups * RD_NW] (zeroed by the kernel's caller)
 hipError_t launch_reduce(const KArgs& a, int groups, double* red, hipStream_t s);
+// flattens each target's sector tilt logw[T * (cap + 1)] from the pilot histogram
+hipError_t launch_tilt(int T, int cap, const int32_t* n0, const uint32_t* hist, double* logw, double max_logw,
+                       double floor_push, hipStream_t s);
+// dlogI[T * P] = score[t][1 + j] / score[t][0] (score rows of 1 + P doubles)
+hipError_t launch_dlogi(int T, int P, const double* score, double* dlogI, hipStream_t s);
+// p[0 .. n) = v by a kernel (no memset node under graph capture)
+hipError_t fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
+hipError_t fill_f64(double* p, size_t n, double v, hipStream_t s);
 
 } // namespace rj

@@ -274,7 +274,7 @@ template <class R> struct ScoreWalker {
     __device__ __forceinline__ double finish(const Tgt<R>& T, V3<R>& g_nm2, V3<R>& g_nm1) {
         // end term on segment n-2 and the end point (gA = vertex n-2, gB = vertex n-1)
         lp += (double)end_term(T, uprev, fprev);
-        V3<R> d = fprev - T.eta;
+        V3<R> d = from_eta(T, fprev);
         R dn2 = dot(d, d);
         R idn = Mth<R>::rsqrt(dn2);
         V3<R> nu = idn * d;
@@ -326,11 +326,13 @@ struct StepCtx {
     uint32_t chain, k0, k1;
     int cap;
     uint32_t bthresh;
-    float log_pb, log_pd;
+    double log_pb, log_pd; // log of the birth / death probabilities of a jump step
     double sigma, ikappa, e2k, mala_h;
     int sampler;
     const double* logw;
+    uint32_t* hist; // this target's sector histogram (cap + 1 counts) or NULL
 };
+
 
 
 // log rho(nu) of the paper's angular response (0 for a uniform response)
@@ -392,6 +394,7 @@ template <class R> struct Lane {
     // lazily: `run` counts the counted steps spent at the current n and is
     // folded in when n changes and at the end of the launch.
     uint32_t run;
+    uint32_t hrun; // steps of this launch at the current n not yet added to the sector histogram
     double a1, a2, sl, sl2;
     uint64_t sn;
     uint32_t cnt, c2, ncap, pp, pb, pd, ap, ab, ad, mp, ma;
@@ -410,6 +413,12 @@ template <class R> __device__ __forceinline__ void fold_run(Lane<R>& ln, int n0,
         ln.a2 += at0 ? a : 0.0;
     }
     ln.run = 0;
+}
+
+// Adds the steps spent at the current n to the sector histogram.
+template <class R> __device__ __forceinline__ void fold_hist(Lane<R>& ln, const StepCtx& sc) {
+    if (sc.hist && ln.hrun) atomicAdd(sc.hist + ln.n, ln.hrun);
+    ln.hrun = 0;
 }
 
 
@@ -527,18 +536,18 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
             const R rho2 = Mth<R>::sqrt((R)-2 * Mth<R>::log(unif<R>(r[6])));
             const V3<R> xi = {rho1 * c5, rho1 * s5, rho2 * Mth<R>::cos2pi(unif<R>(r[7]))};
             const V3<R> fg = fo + (R)sc.sigma * xi;
-            V3<R> dd = fo - T.eta, e2, e3;
+            V3<R> dd = from_eta(T, fo), e2, e3;
             nu = Mth<R>::rsqrt(dot(dd, dd)) * dd; // sensor normal at the current end point
             onb(nu, e2, e3);
             const R omw = -lg * (R)sc.ikappa; // 1 - cos
             const R wv = (R)1 - omw;
             const R sw = Mth<R>::sqrt(fmax(omw * ((R)2 - omw), (R)0));
             nn = wv * nu + sw * (c5 * e2 + s5 * e3); // sensor normal at the proposed end point
-            fn = is_end ? T.eta + T.rad * nn : fg;
+            fn = is_end ? T.eta + (T.eta_lo + T.rad * nn) : fg;
         }
         const Seg<R> Ao = make_seg(T, fm1, fo), An = make_seg(T, fm1, fn);
         const Seg<R> Bo = make_seg(T, fo, fp1), Bn = make_seg(T, fn, fp1);
-        const V3<R> um = unit_dir(fm2, fm1), up = unit_dir(fp1, fp2), nu1 = unit_dir(T.eta, fp1);
+        const V3<R> um = unit_dir(fm2, fm1), up = unit_dir(fp1, fp2), nu1 = unit_dir_eta(T, fp1);
         const LayV<R> lm1 = lay_of(T, fm1), lo = lay_of(T, fo), lnw = lay_of(T, fn), lp1 = lay_of(T, fp1);
         const int km1 = hm2 ? VK_TURN : VK_EMIT;
         const int kj = is_end ? VK_END : VK_TURN;
@@ -652,7 +661,7 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
         fv = birth ? fb : fj;
     }
     const Seg<R> sA = make_seg(T, A, fv), sB = make_seg(T, fv, B);
-    const V3<R> up = unit_dir(fprev, A), un = unit_dir(B, fnext), nuB = unit_dir(T.eta, B);
+    const V3<R> up = unit_dir(fprev, A), un = unit_dir(B, fnext), nuB = unit_dir_eta(T, B);
     const LayV<R> la = lay_of(T, A), lb = lay_of(T, B), lv = lay_of(T, fv);
     const int kA = hprev ? VK_TURN : VK_EMIT, kB = hnext ? VK_TURN : VK_END;
     // (an end point B is the same in x and y: its angular response cancels)
@@ -681,6 +690,7 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
     if (logu < logA) {
         accepted = 1;
         fold_run(ln, T.n0, sc.cap, sc.logw != nullptr); // the steps spent at the old n
+        fold_hist(ln, sc);
         const double dL = (double)sA.len + (double)sB.len - (double)AB.len;
         if (birth) {
             for (int v = n - 1; v >= iB; --v) ps.st(v + 1, ps.ld(v));
@@ -739,8 +749,8 @@ __device__ __forceinline__ void one_step(const KArgs& a, const Tgt<R>& T, const 
         ln.run += 1;
         ln.sl += ln.L;
         ln.sl2 += ln.L * ln.L;
-        if (a.hist && ln.live) atomicAdd(a.hist + (size_t)t * (a.cap + 1) + ln.n, 1u);
     }
+    ln.hrun += 1;
     if (a.trace && ln.live) {
         double* tr = a.trace + ((size_t)c * a.trace_steps + a.trace_off + s) * RJPATH_TRACE_WORDS;
         tr[0] = move;
@@ -818,14 +828,15 @@ __global__ void __launch_bounds__(256) run_kernel(KArgs a) {
     sc.cap = cap;
     sc.bthresh = a.bthresh;
     const double pb = (double)a.bthresh * 0x1p-32;
-    sc.log_pb = (float)log(pb);
-    sc.log_pd = (float)log1p(-pb);
+    sc.log_pb = log(pb);
+    sc.log_pd = log1p(-pb);
     sc.sigma = a.sigma;
     sc.ikappa = 1.0 / a.kappa_end;
     sc.e2k = exp(-2.0 * a.kappa_end);
     sc.mala_h = a.mala_h;
     sc.sampler = a.sampler;
     sc.logw = a.logw ? a.logw + (size_t)t * (cap + 1) : nullptr;
+    sc.hist = a.hist ? a.hist + (size_t)t * (cap + 1) : nullptr;
     ln.invw = 1.0;
     if (sc.logw) {
         ln.lwm = sc.logw[ln.n - 1];
@@ -850,6 +861,7 @@ __global__ void __launch_bounds__(256) run_kernel(KArgs a) {
     }
 
     fold_run(ln, T.n0, cap, sc.logw != nullptr);
+    if (healthy) fold_hist(ln, sc);
     // log p of the final path (refreshed once rather than tracked per step)
     if (healthy) ln.lp = full_logp(T, ps, ln.n, ln.L);
     // write back the LDS part, the vertex count, log p and the statistics

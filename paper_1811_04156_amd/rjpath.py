@@ -49,7 +49,7 @@ class RunParams(C.Structure):
 
 
 EXPORTS = ["rjpath_last_error", "rjpath_version", "rjpath_init_medium", "rjpath_free_medium", "rjpath_run_chains",
-           "rjpath_anchor", "rjpath_intensity", "rjpath_grad", "rjpath_autotune"]
+           "rjpath_anchor", "rjpath_intensity", "rjpath_grad", "rjpath_autotune", "rjpath_tune_tilt", "rjpath_dlogi_dtheta"]
 
 _lib = None
 
@@ -78,6 +78,9 @@ def load(path: str = LIB_PATH):
     L.rjpath_grad.argtypes = [_p, C.POINTER(Targets), C.POINTER(Chains), _p, _p, _p, _p]
     L.rjpath_autotune.argtypes = [_p, C.POINTER(Targets), C.POINTER(Chains), C.POINTER(RunParams), C.c_int32,
                                   C.POINTER(C.c_int32), C.POINTER(C.c_int32), _p]
+    L.rjpath_tune_tilt.argtypes = [_p, C.POINTER(Targets), C.POINTER(Chains), C.POINTER(RunParams), C.c_int32, _p,
+                                   C.c_double, C.c_double, _p]
+    L.rjpath_dlogi_dtheta.argtypes = [_p, C.POINTER(Targets), _p, _p, _p]
     for f in EXPORTS[2:]:
         getattr(L, f).restype = C.c_int
     _lib = L
@@ -262,6 +265,28 @@ class Sampler:
         self.step += steps
         return b.value, v.value
 
+    def tune_tilt(self, rounds=4, steps=400, max_logw=40.0, floor_push=3.0, run=None):
+        """Sector-tilt tuning in librjpath (rjpath_tune_tilt): `rounds` pilot
+        rounds of `steps` steps, the tilt table updated on the device after
+        each; the chains advance, their statistics are left untouched."""
+        if self.logw is None:
+            self.logw = torch.zeros((self.T, self.cap + 1), dtype=torch.float64, device=self.dev)
+        hist = torch.zeros((self.T, self.cap + 1), dtype=torch.int32, device=self.dev)
+        p = self._params(steps, run)
+        tg, ch = self._targets(), self._chains()
+        _check(load().rjpath_tune_tilt(self.medium.h, C.byref(tg), C.byref(ch), C.byref(p), int(rounds), _tp(hist),
+                                       float(max_logw), float(floor_push), self._stream_ptr()))
+        self.step += rounds * steps
+        return self.logw, hist
+
+    def dlogI(self, score):
+        """d log I / d theta (T, L_total, 3) on the device from accumulated
+        score sums (rjpath_dlogi_dtheta)."""
+        out = torch.empty((self.T, 3 * self.medium.L_total), dtype=torch.float64, device=self.dev)
+        tg = self._targets()
+        _check(load().rjpath_dlogi_dtheta(self.medium.h, C.byref(tg), _tp(score), _tp(out), self._stream_ptr()))
+        return out.reshape(self.T, self.medium.L_total, 3)
+
     def anchor(self, refresh=False):
         """Anchor-sector integrals (T,), computed once and cached."""
         if refresh or getattr(self, "_anchor", None) is None:
@@ -282,9 +307,16 @@ class Sampler:
         return dict(I=I, se=se, ess=ess, rhat=rh, anchor=an, code=code)
 
     def grad(self, logp=True, dv=False, score=False):
+        """log p (C,), d log p / d vertices (layout of verts) and the score
+        sums (T, 1 + 3 L_total); `score` may be an existing device tensor of
+        that shape, which the call adds to."""
         lp = torch.full((self.C,), float("nan"), dtype=torch.float64, device=self.dev) if logp else None
         g = torch.zeros_like(self.verts) if dv else None
-        sc = torch.zeros((self.T, 1 + 3 * self.medium.L_total), dtype=torch.float64, device=self.dev) if score else None
+        if isinstance(score, torch.Tensor):
+            sc = score
+        else:
+            sc = torch.zeros((self.T, 1 + 3 * self.medium.L_total), dtype=torch.float64, device=self.dev) \
+                if score else None
         tg, ch = self._targets(), self._chains()
         _check(load().rjpath_grad(self.medium.h, C.byref(tg), C.byref(ch), _tp(lp), _tp(g), _tp(sc),
                                   self._stream_ptr()))

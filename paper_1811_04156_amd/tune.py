@@ -17,33 +17,10 @@ import numpy as np
 
 
 def tune_tilt(s, rounds=4, steps=400, max_logw=40.0, floor_push=3.0):
-    """Sets s.logw by `rounds` pilot runs of `steps` steps (histograms of the
-    sector n after every step).  Returns the (T, cap+1) table."""
-    T, cap = s.T, s.cap
-    n0 = np.asarray(s.w["t_n0"], int)
-    logw = np.zeros((T, cap + 1)) if s.logw is None else s.logw.cpu().numpy().copy()
-    saved = s.stats.clone()
-    for _ in range(rounds):
-        s.set_logw(logw)
-        _, hist = s.run(steps, run=dict(burn_in=0), hist=True)
-        h = hist.cpu().numpy().astype(np.float64)
-        for t in range(T):
-            ht = h[t]
-            if ht.sum() == 0:
-                continue
-            mode = int(np.argmax(ht))
-            lo = int(n0[t])
-            if mode <= lo:
-                continue
-            for n in range(lo, mode):
-                if ht[n] > 0:
-                    logw[t, n] += np.log(ht[mode] / ht[n])
-                else:
-                    logw[t, n] += floor_push
-            np.clip(logw[t], 0.0, max_logw, out=logw[t])
-    s.set_logw(logw)
-    s.stats.copy_(saved)
-    return logw
+    """Sets the sampler's sector tilt by `rounds` pilot rounds of `steps`
+    steps (rjpath_tune_tilt); returns the (T, cap+1) table."""
+    logw, _ = s.tune_tilt(rounds=rounds, steps=steps, max_logw=max_logw, floor_push=floor_push, run=dict(burn_in=0))
+    return logw.cpu().numpy()
 
 
 def tune_launch(s, steps=240, run=None):

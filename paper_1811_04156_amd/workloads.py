@@ -203,7 +203,9 @@ def layered_pairs(seed=3, pairs=1000, chains=1 << 20, cap=512, steps=10_000,
     log-U[40,250] m, g = 0.9); each pair has a cone source (20 deg half-angle,
     horizontal axis, uniform azimuth) at a uniform depth and a sensor at a
     distance ~ U[dmin,dmax] in a uniform direction, kept inside the stack.
-    Chain c belongs to pair c mod pairs."""
+    Chains are assigned to pairs in contiguous runs: chain c belongs to pair
+    floor(c * pairs / chains) (1048 or 1049 chains per pair at 2^20 chains),
+    so a block of chains covers one or two targets."""
     rng = np.random.default_rng(seed)
     lam_s = np.exp(rng.uniform(np.log(10.0), np.log(60.0), n_layers))
     lam_a = np.exp(rng.uniform(np.log(40.0), np.log(250.0), n_layers))
@@ -233,7 +235,7 @@ def layered_pairs(seed=3, pairs=1000, chains=1 << 20, cap=512, steps=10_000,
     tg = _targets(np.zeros(pairs), src, sensor, r, np.full(pairs, emit_kind), axis,
                   param, n, init)
     w = dict(name="layered", cap=int(cap), **media, **tg,
-             c_target=(np.arange(chains) % pairs).astype(np.int32))
+             c_target=(np.arange(chains, dtype=np.int64) * pairs // chains).astype(np.int32))
     w.update(DEFAULT_RUN)
     w.update(seed=seed, steps=steps, burn_in=steps // 10, precision="f32")
     w.update(over)

@@ -90,29 +90,182 @@ def test_tilt_leaves_the_intensity_unchanged(rj):
         assert b["se"][0] / b["I"][0] < a["se"][0] / a["I"][0]
 
 
-def test_fp32_intensity_matches_oracle_estimator(rj):
-    """Config-2 targets: device estimate (many chains) vs the oracle's
-    estimator (fewer chains), within 3.5 combined standard errors."""
+def test_fp32_intensity_within_1pct_and_3sigma_of_oracle(rj):
+    """Config-2 targets (the six nearest, 5.5-6.5 m): the device estimate
+    (FP32 evaluation, 16,384 chains per target) and the oracle's estimator
+    (FP64, 512 chains per target, its own independent random streams) agree
+    within 1% and within 3 combined standard errors, target by target."""
     from oracle import oracle as O
     w = W.config2(groups=256, per_group=1)
-    pick = [int(t) for t in np.argsort(np.linalg.norm(w["t_sensor"], axis=1))[:6]]  # the nearest targets
+    pick = [int(t) for t in np.argsort(np.linalg.norm(w["t_sensor"], axis=1))[:6]]
     wg = dict(w)
-    wg["c_target"] = np.repeat(np.array(pick, np.int32), 4096)
+    wg["c_target"] = np.repeat(np.array(pick, np.int32), 16384)
     wg["burn_in"] = 0
     s = rj.Sampler(wg, precision="f32")
     s.run(3000)  # burn-in from the straight starting path
     s.stats.zero_()
-    s.run(4000)
+    s.run(8000)
     res = s.intensity(groups=16)
-    # the oracle on its own chains (stream ids offset so the two samples are independent)
     wo = dict(w)
-    wo["c_target"] = np.repeat(np.array(pick, np.int32), 256)
-    wo["burn_in"] = 3000
+    wo["c_target"] = np.repeat(np.array(pick, np.int32), 512)
+    wo["burn_in"] = 2000
     orc = O.Oracle(wo)
     st = O.initial_state(wo)
-    stats, _ = orc.run(wo, st, 7000, chain_ids=np.arange(len(wo["c_target"])) + 1_000_000)
-    anchors = [orc.anchor_I2(t) for t in range(len(w["t_src"]))]
+    stats, _ = orc.run(wo, st, 12000, chain_ids=np.arange(len(wo["c_target"])) + 1_000_000)
+    anchors = [orc.anchor_I2(t) if t in pick else 0.0 for t in range(len(w["t_src"]))]
     Io, seo = O.intensity(wo, stats, anchors)
     for t in pick:
         assert res["anchor"][t] == pytest.approx(anchors[t], rel=1e-6)
-        assert abs(res["I"][t] - Io[t]) < 3.5 * math.hypot(res["se"][t], seo[t]), (t, res["I"][t], Io[t])
+        d = res["I"][t] - Io[t]
+        sig = math.hypot(res["se"][t], seo[t])
+        print(f"target {t}: device {res['I'][t]:.6e} +- {res['se'][t] / res['I'][t]:.2%}, oracle {Io[t]:.6e} "
+              f"+- {seo[t] / Io[t]:.2%}, diff {d / Io[t]:+.3%} = {d / sig:+.2f} sigma")
+        assert abs(d) < 3 * sig, (t, res["I"][t], Io[t], sig)
+        assert abs(d) < 0.01 * Io[t], (t, res["I"][t], Io[t])
+
+
+def _golden_anchor():
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "layered_cone_anchor.txt")
+    rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+    return {int(r[0]): (int(r[1]), [float(x) for x in r[2:]]) for r in rows}
+
+
+def test_layered_cone_targets_ratio_and_anchor(rj):
+    """Cone sources in the 100-layer medium, whose anchor sector is n0 = 3
+    (the sensor lies outside the emission cone): the Monte-Carlo ratio
+    R = E[1/w] / E[1(n = 3) / w(3)] of the device (FP32, 16,384 chains per
+    target) and of the oracle (FP64, 512 chains) agree within 1% and 3
+    combined standard errors, and the device's I_3 quadrature agrees with the
+    oracle's converged value (tests/golden/layered_cone_anchor.txt, three
+    resolutions on record) within 2e-3, so I = I_3 R agrees within their sum."""
+    from oracle import oracle as O
+    gold = _golden_anchor()
+    pick = [877, 364]
+    w = W.layered_pairs(seed=3, pairs=1000, chains=1000, cap=512)
+    for t in pick:
+        assert w["t_n0"][t] == 3 and gold[t][0] == 3
+        lo, mid, hi = gold[t][1]
+        assert abs(mid / hi - 1) < 5e-4  # the oracle's own rule has converged here
+    wg = dict(w)
+    wg["c_target"] = np.repeat(np.array(pick, np.int32), 16384)
+    wg["burn_in"] = 0
+    s = rj.Sampler(wg, precision="f32")
+    s.run(3000)
+    s.stats.zero_()
+    s.run(8000)
+    an = s.anchor()
+    s._anchor = np.ones(len(w["t_src"]))  # the ratio alone
+    res = s.intensity(groups=16)
+    wo = dict(w)
+    wo["c_target"] = np.repeat(np.array(pick, np.int32), 512)
+    wo["burn_in"] = 2000
+    orc = O.Oracle(wo)
+    st = O.initial_state(wo)
+    stats, _ = orc.run(wo, st, 16000, chain_ids=np.arange(len(wo["c_target"])) + 2_000_000)
+    Ro, seo = O.intensity(wo, stats, np.ones(len(w["t_src"])))
+    for t in pick:
+        hi = gold[t][1][2]
+        ea = an[t] / hi - 1
+        d = res["I"][t] - Ro[t]
+        sig = math.hypot(res["se"][t], seo[t])
+        print(f"target {t}: anchor device/oracle - 1 = {ea:+.2e}; ratio device {res['I'][t]:.5f} "
+              f"+- {res['se'][t] / res['I'][t]:.2%}, oracle {Ro[t]:.5f} +- {seo[t] / Ro[t]:.2%}, "
+              f"diff {d / Ro[t]:+.3%} = {d / sig:+.2f} sigma")
+        assert abs(ea) < 2e-3, (t, an[t], hi)
+        assert abs(d) < 3 * sig, (t, res["I"][t], Ro[t], sig)
+        assert abs(d) < 0.01 * Ro[t], (t, res["I"][t], Ro[t])
+
+
+def test_tilt_kernel_follows_its_rule(rj):
+    """rjpath_tune_tilt: after each pilot round the device raises log w(n) by
+    log(h(mode) / h(n)) for n0 <= n < mode (floor_push where h(n) = 0) and
+    clamps to [0, max_logw]; replayed here in numpy from the returned
+    histogram of the last round, and the chain statistics are untouched."""
+    w = W.config2(groups=16, per_group=256, cap=64)
+    w["burn_in"] = 0
+    s = rj.Sampler(w, precision="f32")
+    s.run(200)
+    before = s.stats.clone()
+    logw1, _ = s.tune_tilt(rounds=1, steps=300, max_logw=6.0, floor_push=2.0)
+    lw_prev = logw1.cpu().numpy().copy()
+    logw2, hist = s.tune_tilt(rounds=1, steps=300, max_logw=6.0, floor_push=2.0)
+    torch.cuda.synchronize()
+    assert torch.equal(before, s.stats)
+    h = hist.cpu().numpy().astype(np.int64)
+    assert np.all(h.sum(1) == 256 * 300)
+    ref = lw_prev.copy()
+    n0 = np.asarray(w["t_n0"])
+    for t in range(s.T):
+        mode = int(np.argmax(h[t]))
+        for n in range(int(n0[t]), mode):
+            ref[t, n] += np.log(h[t, mode] / h[t, n]) if h[t, n] > 0 else 2.0
+        ref[t] = np.clip(ref[t], 0.0, 6.0)
+    assert np.allclose(logw2.cpu().numpy(), ref, rtol=1e-13, atol=1e-13)
+    assert s.step == 200 + 600
+
+
+def test_dlogi_dtheta_is_the_score_ratio(rj):
+    """rjpath_dlogi_dtheta divides the accumulated score sums by the sample
+    weight per target (and gives NaN for a target without samples)."""
+    w = W.layered_pairs(pairs=4, chains=1024, cap=64, n_layers=12, dz=6.0, dmin=5.0, dmax=20.0)
+    s = rj.Sampler(w, precision="f32")
+    s.run(300)
+    score = torch.zeros((s.T, 1 + 3 * s.medium.L_total), dtype=torch.float64, device=s.dev)
+    for _ in range(3):
+        s.run(100)
+        s.grad(logp=False, score=score)
+    d = s.dlogI(score).cpu().numpy()
+    sc = score.cpu().numpy()
+    assert np.allclose(d.reshape(s.T, -1), sc[:, 1:] / sc[:, :1], rtol=1e-15, atol=0)
+    zero = torch.zeros_like(score)
+    assert np.all(np.isnan(s.dlogI(zero).cpu().numpy()))
+
+
+def test_autotune_follows_the_default_trajectory(rj):
+    """rjpath_autotune: its trial launches are ordinary sampler steps, so a
+    run through the tuner ends in exactly the state of a run with the default
+    launch; the chosen launch, timed afterwards on that same state, is no
+    slower than the default launch (10% timing noise allowed)."""
+    import time
+    w = W.layered_pairs(pairs=256, chains=1 << 17, cap=64)
+    w["burn_in"] = 0
+    a = rj.Sampler(w, precision="f32")
+    b = rj.Sampler(w, precision="f32")
+    a.run(100)
+    b.run(100)
+    blk, v = a.autotune(4400)
+    b.run(4400)
+    torch.cuda.synchronize()
+    assert blk in (64, 256) and 1 <= v <= 64
+    assert torch.equal(a.n, b.n)
+    used = (torch.arange(a.cap, device=a.n.device)[:, None] < a.n[None, :])[..., None]
+    assert torch.equal(a.verts[..., :3] * used, b.verts[..., :3] * used)
+
+    def timed(smp):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        smp.run(300)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    # a's handle holds the tuned launch, b's the default; the two chains stay
+    # identical, so every timing pair runs the same work
+    ta, tb = [], []
+    for _ in range(3):
+        ta.append(timed(a))
+        tb.append(timed(b))
+    assert torch.equal(a.n, b.n)
+    print(f"autotune chose block {blk}, v_lds {v}: {min(ta) * 1e3:.2f} ms vs default {min(tb) * 1e3:.2f} ms")
+    assert min(ta) <= 1.10 * min(tb)
+
+
+def test_autograd_on_device_theta(rj):
+    """The autograd wrapper returns the gradient on theta's own device and dtype."""
+    from paper_1811_04156_amd.autograd import RJPathIntensity
+    w = W.single_target(2.0, 0.165, math.inf, 20.0, 0.9, chains=256, cap=8, seed=2)
+    theta = torch.tensor([[math.inf, 20.0, 0.9]], dtype=torch.float64, device="cuda", requires_grad=True)
+    I = RJPathIntensity.apply(theta, w, dict(chunks=1, chunk_steps=100, burn_in=50, tilt=False))
+    I.sum().backward()
+    assert theta.grad.device == theta.device and theta.grad.dtype == theta.dtype
+    assert theta.grad[0, 1].item() > 0

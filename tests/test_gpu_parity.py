@@ -1,9 +1,17 @@
-"""Parity of the HIP path (through the C ABI) with the FP64 oracle."""
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances (the contract): per-path log p within 1e-4 absolute in FP32 (1e-9
+in FP64); vertex gradients within 1e-3 relative in FP32; accept decisions
+identical wherever |log u - log A| exceeds the a-priori FP32 error bound of
+that proposal's log A (gpu_helpers.fp32_logA_bound), and |Delta log A| within
+that bound for every proposal; FP64 runs take identical decisions and end in
+the oracle's paths."""
 import math
 
 import numpy as np
 import pytest
 
+from gpu_helpers import lockstep, mixed_workload, random_paths
 from paper_1811_04156_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -20,66 +28,17 @@ def rj():
     return rjpath
 
 
-def _mixed_workload(cap=48, chains=256, seed=5):
-    """Layered medium, 8 pairs: isotropic, vMF and cone sources, both detection kinds."""
-    w = W.layered_pairs(seed=seed, pairs=8, chains=chains, cap=cap, n_layers=12, dz=6.0, dmin=5.0, dmax=30.0,
-                        emit_kind=W.EMIT_ISO)
-    kind = np.array([0, 1, 2, 0, 1, 2, 0, 0], np.int32)
-    param = np.array([0, 3.0, math.radians(60), 0, 8.0, math.radians(75), 0, 0])
-    det = np.array([0, 1, 0, 1, 0, 1, 0, 1], np.int32)
-    src, sen, rad, ax = w["t_src"], w["t_sensor"], w["t_radius"], w["t_emit_dir"]
-    n_init, init = W._cone_start(src, sen, rad, ax, np.where(kind == 2, param, np.pi))
-    w.update(W._targets(w["t_medium"], src, sen, rad, kind, ax, param, n_init, init, det,
-                        np.tile([0.0, -1.0, 0.0], (8, 1))))
-    w["f_sl"] = np.where(np.arange(12) % 3 == 0, 0.45, 0.0)
-    w["g"] = np.linspace(0.8, 0.95, 12)
-    return w
-
-
-def _random_paths(orc, w, rng, nmax):
-    """Random ragged paths with finite density (n in [2, nmax])."""
-    C = len(w["c_target"])
-    cap = int(w["cap"])
-    n = np.zeros(C, np.int32)
-    V = np.zeros((C, cap, 3))
-    for c in range(C):
-        t = int(w["c_target"][c])
-        eta = w["t_sensor"][t] - w["t_src"][t]
-        R = w["t_radius"][t]
-        ax = w["t_emit_dir"][t]
-        for _ in range(200):
-            k = int(rng.integers(2, nmax + 1))
-            v = np.zeros((k, 3))
-            if k > 2:
-                d = ax * rng.uniform(1, 4) + rng.normal(size=3) * 0.3
-                v[1] = d
-                for i in range(2, k - 1):
-                    v[i] = v[i - 1] + (eta - v[i - 1]) / (k - i) + rng.normal(size=3) * 1.5
-            dd = v[k - 2] - eta
-            dd /= np.linalg.norm(dd)
-            e = dd + 0.4 * rng.normal(size=3)
-            e /= np.linalg.norm(e)
-            if e @ dd < 0.3:
-                e = dd
-            v[k - 1] = eta + R * e
-            if np.isfinite(orc.logp(t, v)):
-                break
-        n[c] = k
-        V[c, :k] = v
-    return n, V
-
-
 def _oracle(w):
     from oracle import oracle as O
     return O, O.Oracle(w)
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_logp_and_gradient_parity(rj, prec):
-    w = _mixed_workload()
+@pytest.mark.parametrize("prec,nmax,cap", [("f64", 40, 48), ("f32", 40, 48), ("f32", 160, 192)])
+def test_logp_and_gradient_parity(rj, prec, nmax, cap):
+    w = mixed_workload(cap=cap, chains=256 if nmax <= 40 else 128)
     O, orc = _oracle(w)
     rng = np.random.default_rng(1)
-    n, V = _random_paths(orc, w, rng, 40)
+    n, V = random_paths(orc, w, rng, nmax)
     s = rj.Sampler(w, precision=prec)
     s.set_state(n, V)
     lp, g, sc = s.grad(logp=True, dv=True, score=True)
@@ -89,29 +48,39 @@ def test_logp_and_gradient_parity(rj, prec):
     sc = sc.cpu().numpy()
     n2, V2 = s.get_state()  # the precision's own rounding of the inputs
     tol = 1e-9 if prec == "f64" else 1e-4
+    gtol = 1e-9 if prec == "f64" else 1e-3
     L = len(w["lam_s"])
     score_ref = np.zeros((len(w["t_src"]), 1 + 3 * L))
+    worst = 0.0
     for c in range(len(n)):
         t = int(w["c_target"][c])
         path = V2[c, : n2[c]]
         ref = orc.logp(t, path)
-        assert abs(lp[c] - ref) <= tol * max(1.0, 0.01 * abs(ref)), (c, n2[c], lp[c], ref)
+        assert abs(lp[c] - ref) <= tol, (c, n2[c], lp[c], ref)
         gv, ds, da, dg = orc.grad(t, path)
+        # relative to the path's largest vertex gradient, and per vertex
         scale = np.abs(gv[1:]).max()
-        err = np.abs(g[c, 1 : n2[c]] - gv[1:]).max() / scale
-        assert err < (1e-9 if prec == "f64" else 2e-3), (c, err)
+        err = np.abs(g[c, 1: n2[c]] - gv[1:]).max() / scale
+        assert err < gtol, (c, err)
+        gn = np.linalg.norm(gv[1:], axis=1)
+        ev = np.linalg.norm(g[c, 1: n2[c]] - gv[1:], axis=1) / np.maximum(gn, 1e-3 * gn.max())
+        assert ev.max() < gtol, (c, ev.max())
+        worst = max(worst, ev.max())
         score_ref[t, 0] += 1
         score_ref[t, 1::3] += ds
         score_ref[t, 2::3] += da
         score_ref[t, 3::3] += dg
     rel = np.abs(sc - score_ref) / (np.abs(score_ref) + 1e-6 * np.abs(score_ref).max())
     assert rel.max() < (1e-8 if prec == "f64" else 1e-3), rel.max()
+    print(f"{prec} nmax={nmax}: worst per-vertex gradient error {worst:.2e}")
 
 
-def test_fp64_free_run_matches_oracle(rj):
+@pytest.mark.parametrize("birth_frac", [0.5, 0.3])
+def test_fp64_free_run_matches_oracle(rj, birth_frac):
     """Config 1 (FP64): the device run and the oracle take the same decisions
-    step by step, end in the same paths and accumulate the same statistics."""
-    w = W.config1(burn_in=300)
+    step by step, end in the same paths and accumulate the same statistics
+    (and with an uneven birth/death mix, whose probabilities then enter log A)."""
+    w = W.config1(burn_in=300, birth_frac=birth_frac)
     steps = 2000
     s = rj.Sampler(w, precision="f64")
     tr, _ = s.run(steps, trace=True)
@@ -126,7 +95,7 @@ def test_fp64_free_run_matches_oracle(rj):
     assert np.allclose(gtr[..., 4], otr[..., 4], rtol=1e-14, atol=1e-15)
     fin = np.isfinite(otr[..., 3])
     assert np.array_equal(np.isfinite(gtr[..., 3]), fin)
-    assert np.allclose(gtr[..., 3][fin], otr[..., 3][fin], atol=1e-8, rtol=1e-9)
+    assert np.allclose(gtr[..., 3][fin], otr[..., 3][fin], atol=1e-9, rtol=1e-9)
     assert np.array_equal(gtr[..., 1], otr[..., 1])
     n, V = s.get_state()
     assert np.array_equal(n, st["n"])
@@ -142,6 +111,36 @@ def test_fp64_free_run_matches_oracle(rj):
     I_ref = orc.anchor_I2(0) * ostats[:, 1].sum() / ostats[:, 2].sum()
     assert res["anchor"][0] == pytest.approx(orc.anchor_I2(0), rel=1e-10)
     assert res["I"][0] == pytest.approx(I_ref, rel=1e-10)
+
+
+def test_fp64_layered_free_run_matches_oracle(rj):
+    """FP64 on the layered medium (layer crossings, simplified-Liu layers, vMF
+    and cone sources, the paper's sensor response): identical decisions and
+    paths, step by step."""
+    w = mixed_workload(cap=32, chains=64)
+    w.update(burn_in=100, seed=17)
+    steps = 1000
+    s = rj.Sampler(w, precision="f64")
+    tr, _ = s.run(steps, trace=True)
+    torch.cuda.synchronize()
+    O, orc = _oracle(w)
+    st = O.initial_state(w)
+    ostats, otr = orc.run(w, st, steps, trace=True)
+    gtr = tr.cpu().numpy()
+    assert np.array_equal(gtr[..., 0], otr[..., 0])
+    assert np.array_equal(gtr[..., 2], otr[..., 2])
+    fin = np.isfinite(otr[..., 3])
+    assert np.array_equal(np.isfinite(gtr[..., 3]), fin)
+    assert np.allclose(gtr[..., 3][fin], otr[..., 3][fin], atol=1e-8, rtol=1e-9)
+    assert np.array_equal(gtr[..., 1], otr[..., 1])
+    assert (otr[..., 1] == 1).sum() > 20000
+    n, V = s.get_state()
+    assert np.array_equal(n, st["n"])
+    for c in range(64):
+        assert np.allclose(V[c, : n[c]], st["verts"][c, : n[c]], atol=1e-8)
+    gst = s.stats.cpu().numpy()
+    counts = [0, 5, 6, 7, 8, 9, 10, 11, 12]
+    assert np.array_equal(gst[:, counts], ostats[:, counts])
 
 
 def test_fp64_mala_free_run_matches_oracle(rj):
@@ -169,58 +168,48 @@ def test_fp64_mala_free_run_matches_oracle(rj):
     assert np.array_equal(gst[:, 13:15], ostats[:, 13:15])
 
 
-@pytest.mark.parametrize("which", ["homog", "mixed", "mala"])
-def test_fp32_lockstep_replay(rj, which):
-    """FP32 device steps replayed on the oracle from the device's own state:
-    identical proposals and decisions wherever |log u - log A| > 1e-4."""
+def _lockstep_workload(which):
     if which == "homog":
         w = W.single_target(12.0, 0.165, 20.0, 80.0, 0.9, chains=64, cap=32, burn_in=0, seed=9)
-    elif which == "mala":
-        w = _mixed_workload(cap=32, chains=64)
-        w.update(burn_in=0, seed=6, sampler=1, mala_h=0.01)
-    else:
-        w = _mixed_workload(cap=32, chains=64)
-        w.update(burn_in=0, seed=4)
-    O, orc = _oracle(w)
-    s = rj.Sampler(w, precision="f32")
-    s.run(50)  # leave the starting paths
-    agree = total = 0
-    dA = []
-    for it in range(120):
-        n0, V0 = s.get_state()
-        step = s.step
-        tr, _ = s.run(1, trace=True)
-        g = tr.cpu().numpy()[:, 0]
-        n1, V1 = s.get_state()
-        status = s.status.cpu().numpy()
-        assert status.sum() == 0
-        for c in range(len(n0)):
-            t = int(w["c_target"][c])
-            n, v, rec = orc.step(w, c, t, int(n0[c]), V0[c], step)
-            assert g[c, 0] == rec[0] and g[c, 4] == pytest.approx(rec[4], abs=2e-6)
-            same_choice = g[c, 2] == rec[2]
-            if not same_choice:
-                continue  # segment choice at a cumulative-depth boundary
-            assert np.isfinite(g[c, 3]) == np.isfinite(rec[3])
-            d = abs(g[c, 3] - rec[3]) if np.isfinite(rec[3]) else 0.0
-            dA.append(d / max(1.0, abs(rec[3])))
-            # decisions must agree away from the threshold; "away" is 1e-4 or
-            # twice the FP32 discrepancy of this proposal's log A, whichever is larger
-            if abs(rec[3] - rec[4]) > max(1e-4, 2 * d) or not np.isfinite(rec[3]):
-                total += 1
-                agree += g[c, 1] == rec[1]
-                if g[c, 1] == rec[1]:
-                    assert n1[c] == n
-                    assert np.allclose(V1[c, :n], v, atol=2e-4, rtol=1e-5)
-    dA = np.array(dA)
-    # FP32 log A: typically ~1e-6; short segments next to a focus are ill-conditioned
-    assert np.quantile(dA, 0.99) < 1e-3 and np.median(dA) < 2e-5, (np.quantile(dA, [0.5, 0.99, 1.0]))
-    assert total > 5000
-    assert agree == total
+        return w, {}
+    if which == "overflow":
+        # the 100-layer medium of the ragged-batch workload at cap 512, with 4 LDS
+        # vertex slots per chain so that most paths continue in HBM
+        w = W.layered_pairs(seed=3, pairs=1000, chains=64 * 1000, cap=512)
+        w["c_target"] = np.repeat(np.arange(8, dtype=np.int32) * 125, 8)
+        w.update(burn_in=0, seed=13)
+        return w, dict(block=64, v_lds=4, burn=400)
+    w = mixed_workload(cap=32, chains=64)
+    w.update(burn_in=0, seed=6 if which == "mala" else 4)
+    if which == "mala":
+        w.update(sampler=1, mala_h=0.01)
+    return w, {}
+
+
+@pytest.mark.parametrize("which", ["homog", "mixed", "mala", "overflow"])
+def test_fp32_lockstep_replay(rj, which):
+    """FP32 device steps replayed on the oracle from the device's own state:
+    identical moves and proposals, |Delta log A| within the a-priori FP32
+    bound of every proposal (maximum, not a quantile), identical decisions
+    wherever |log u - log A| exceeds that bound, at most two birth-segment
+    choices differing (a cumulative-depth boundary within FP32 rounding)."""
+    w, kw = _lockstep_workload(which)
+    burn = kw.pop("burn", 50)
+    r = lockstep(rj, w, steps=120 if which != "overflow" else 100, burn=burn, **kw)
+    assert r["compared"] > 4000
+    assert r["ratio"].max() <= 1.0, (r["ratio"].max(), np.quantile(r["dA"], [0.5, 0.99, 1.0]))
+    assert r["agree"] == r["total"], (r["agree"], r["total"])
+    assert r["total"] > 5000
+    assert r["seg_mismatch"] <= 2, r["seg_mismatch"]
+    if which == "overflow":
+        assert r["n_max"] > 4 + 8  # paths well past the LDS slots
+    print(f"{which}: {r['compared']} compared, max |dlogA| {r['dA'].max():.2e}, max ratio to bound "
+          f"{r['ratio'].max():.3f}, {r['near']} near the threshold, {r['seg_mismatch']} segment mismatches, "
+          f"n_max {r['n_max']}")
 
 
 def test_launch_configuration_and_resume_invariance(rj):
-    w = _mixed_workload(cap=40, chains=512)
+    w = mixed_workload(cap=40, chains=512)
     w.update(burn_in=10)
     ref = rj.Sampler(w, precision="f32")
     ref.run(300, block=64, v_lds=4)
@@ -262,7 +251,7 @@ def test_default_launch_at_two_waves_per_simd(rj, kind):
 
 
 def test_anchor_parity(rj):
-    w = _mixed_workload(cap=16, chains=64)
+    w = mixed_workload(cap=16, chains=64)
     O, orc = _oracle(w)
     s = rj.Sampler(w, precision="f32")
     s.run(20)
@@ -275,7 +264,7 @@ def test_anchor_parity(rj):
         else:
             # single-scatter sector: compared where the oracle's own product rule
             # has converged (a sensor a few degrees outside the cone edge needs
-            # more nodes than either rule uses; see the design notes)
+            # more nodes than either rule uses)
             lo = orc.anchor_I3(t, 24, 24, 16, 10, 10)
             hi = orc.anchor_I3(t, 40, 40, 24, 12, 12)
             if abs(lo / hi - 1) < 2e-3:
@@ -312,16 +301,18 @@ def test_cap_is_respected(rj):
     assert stats[:, 12].sum() > 0  # the cap is visited and counted
 
 
-def test_config2_full_size_sampled(rj):
-    """Config 2 at full chain count (65,536 chains, cap 256) for 500 steps:
-    sampled chains' paths re-evaluated by the oracle, cached log p drift,
-    invariants over all chains."""
-    w = W.config2()
+@pytest.mark.parametrize("which", ["config2", "config3"])
+def test_full_size_sampled(rj, which):
+    """The full chain counts (65,536 chains at cap 256; 2^20 chains over 1000
+    layered pairs at cap 512) in the default launch: sampled chains' paths
+    re-evaluated by the oracle to 1e-4, cached log p drift, invariants over
+    all chains."""
+    w = W.config2() if which == "config2" else W.config3()
     s = rj.Sampler(w, precision="f32")
     s.run(500)
     torch.cuda.synchronize()
     n = s.n.cpu().numpy()
-    assert n.min() >= 2 and n.max() <= 256
+    assert n.min() >= 2 and n.max() <= int(w["cap"])
     assert s.status.sum().item() == 0
     lp_cached = s.logp.cpu().numpy()
     lp, _, _ = s.grad()
@@ -329,9 +320,11 @@ def test_config2_full_size_sampled(rj):
     assert np.all(np.isfinite(lp))
     assert np.max(np.abs(lp - lp_cached)) < 5e-3
     O, orc = _oracle(w)
-    nn, V = s.get_state()
     rng = np.random.default_rng(0)
-    for c in rng.choice(len(n), 128, replace=False):
+    idx = rng.choice(len(n), 128, replace=False)
+    nn = n[idx]
+    V = s.verts[: int(nn.max()), torch.as_tensor(idx, device=s.verts.device), :3].permute(1, 0, 2).cpu().numpy()
+    for i, c in enumerate(idx):
         t = int(w["c_target"][c])
-        ref = orc.logp(t, V[c, : nn[c]])
-        assert abs(lp[c] - ref) < 1e-4 * max(1.0, 0.01 * abs(ref)), (c, lp[c], ref)
+        ref = orc.logp(t, V[i, : nn[i]].astype(np.float64))
+        assert abs(lp[c] - ref) < 1e-4, (c, lp[c], ref)
