@@ -235,6 +235,22 @@ int rjpath_anchor(rjpath_medium* m, const rjpath_targets* t, double* anchor, voi
 int rjpath_intensity(rjpath_medium* m, const rjpath_targets* t, const rjpath_chains* c, int32_t groups,
                      const double* anchor, double* I, double* se, double* ess, double* rhat, void* stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): rjpath_intensity with no
+ * allocation, no host synchronisation and no copy.  Its reduction buffer
+ * (and the anchors, when `anchor` is NULL) live in a static device array of
+ * 512 Ki doubles (4 MiB) per GPU, held until the process ends; it requires
+ * n_targets * groups * 6 (+ n_targets when anchor is NULL) <= 524288, else
+ * RJPATH_EINVAL.  anchor: NULL (computed here) or device, n_targets doubles.
+ * I, se, ess, rhat: device, n_targets doubles each (any may be NULL), written
+ * by a device finalisation identical in arithmetic to rjpath_intensity's; a
+ * target without anchor-sector visits gets NaN (no RJPATH_ENODATA, since
+ * nothing is read back).  Asynchronous on `stream`.  Every call on one GPU
+ * uses that GPU's one buffer: calls that overlap on a GPU (other streams,
+ * other threads) race and must be serialised by the caller. */
+int rjpath_intensity_noalloc(rjpath_medium* m, const rjpath_targets* t, const rjpath_chains* c, int32_t groups,
+                             const double* anchor, double* I, double* se, double* ess, double* rhat, void* stream);
+
 /* Score of the current paths, recomputed from the vertices (no stored tape):
  *  logp_out[C]      (device, may be NULL): log p of each path, FP64 sum
  *  dlogp_dv         (device, may be NULL): d log p / d vertex, layout of verts,

@@ -549,6 +549,23 @@ int rjpath_anchor(rjpath_medium* m, const rjpath_targets* t, double* anchor, voi
     return RJPATH_OK;
 }
 
+int rjpath_intensity_noalloc(rjpath_medium* m, const rjpath_targets* t, const rjpath_chains* c, int32_t groups,
+                             const double* anchor, double* I, double* se, double* ess, double* rhat, void* stream) {
+    int r = check_common(m, t, c);
+    if (r) return r;
+    if (groups < 2 || groups > 64) return fail(RJPATH_EINVAL, "groups must lie in [2, 64]");
+    const size_t need = (size_t)t->n_targets * groups * RD_NW + (anchor ? 0 : (size_t)t->n_targets);
+    const size_t cap = noalloc_scratch_doubles();
+    if (need > cap)
+        return fail(RJPATH_EINVAL, "rjpath_intensity_noalloc: n_targets * groups * 6 (+ n_targets without anchors) = " +
+                                       std::to_string(need) + " doubles exceeds its static buffer of " +
+                                       std::to_string(cap));
+    KArgs a = make_args(m, t, c);
+    HIPCHK(launch_intensity_noalloc(a, groups, anchor, m->d_gl, I, se, ess, rhat, (hipStream_t)stream),
+           "rjpath_intensity_noalloc kernels");
+    return RJPATH_OK;
+}
+
 int rjpath_intensity(rjpath_medium* m, const rjpath_targets* t, const rjpath_chains* c, int32_t groups,
                      const double* anchor, double* I, double* se, double* ess, double* rhat, void* stream) {
     int r = check_common(m, t, c);

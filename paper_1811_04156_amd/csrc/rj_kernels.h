@@ -40,5 +40,10 @@ hipError_t launch_dlogi(int T, int P, const double* score, double* dlogI, hipStr
 // p[0 .. n) = v by a kernel (no memset node under graph capture)
 hipError_t fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
 hipError_t fill_f64(double* p, size_t n, double v, hipStream_t s);
+// the intensity estimator with its buffers in a per-GPU static device array
+// (rj_noalloc.hip): reduction, anchors if `anchor` is NULL, device finalisation
+size_t noalloc_scratch_doubles();
+hipError_t launch_intensity_noalloc(const KArgs& a, int groups, const double* anchor, const double* gl, double* I,
+                                    double* se, double* ess, double* rhat, hipStream_t s);
 
 } // namespace rj

@@ -49,7 +49,8 @@ class RunParams(C.Structure):
 
 
 EXPORTS = ["rjpath_last_error", "rjpath_version", "rjpath_init_medium", "rjpath_free_medium", "rjpath_run_chains",
-           "rjpath_anchor", "rjpath_intensity", "rjpath_grad", "rjpath_autotune", "rjpath_tune_tilt", "rjpath_dlogi_dtheta"]
+           "rjpath_anchor", "rjpath_intensity", "rjpath_grad", "rjpath_autotune", "rjpath_tune_tilt", "rjpath_dlogi_dtheta",
+           "rjpath_intensity_noalloc"]
 
 _lib = None
 
@@ -81,6 +82,8 @@ def load(path: str = LIB_PATH):
     L.rjpath_tune_tilt.argtypes = [_p, C.POINTER(Targets), C.POINTER(Chains), C.POINTER(RunParams), C.c_int32, _p,
                                    C.c_double, C.c_double, _p]
     L.rjpath_dlogi_dtheta.argtypes = [_p, C.POINTER(Targets), _p, _p, _p]
+    L.rjpath_intensity_noalloc.argtypes = [_p, C.POINTER(Targets), C.POINTER(Chains), C.c_int32, _p, _p, _p, _p, _p,
+                                           _p]
     for f in EXPORTS[2:]:
         getattr(L, f).restype = C.c_int
     _lib = L
@@ -305,6 +308,16 @@ class Sampler:
                                        _np_ptr(I), _np_ptr(se), _np_ptr(ess), _np_ptr(rh), self._stream_ptr())
         _check(code, allow=(RJPATH_ENODATA,))
         return dict(I=I, se=se, ess=ess, rhat=rh, anchor=an, code=code)
+
+    def intensity_noalloc(self, groups=16, anchor=None):
+        """rjpath_intensity_noalloc: the estimator with every buffer in the
+        library's static device array; returns device tensors (I, se, ess,
+        rhat).  anchor: None (computed on the device) or a (T,) device tensor."""
+        out = [torch.empty(self.T, dtype=torch.float64, device=self.dev) for _ in range(4)]
+        tg, ch = self._targets(), self._chains()
+        _check(load().rjpath_intensity_noalloc(self.medium.h, C.byref(tg), C.byref(ch), int(groups), _tp(anchor),
+                                               *[_tp(x) for x in out], self._stream_ptr()))
+        return dict(zip(("I", "se", "ess", "rhat"), out))
 
     def grad(self, logp=True, dv=False, score=False):
         """log p (C,), d log p / d vertices (layout of verts) and the score
