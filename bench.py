@@ -1,22 +1,30 @@
 """Throughput benchmark of the batched reversible-jump photon-path sampler.
 
-Workload: 65,536 chains in 256 groups of 256 (one source/sensor pair and one
-homogeneous medium per group: scattering length log-U[10,50] m, absorption
-length log-U[50,200] m, g ~ U[0.8,0.95], sensor radius 0.165 m at U[5,100] m),
-vertex cap 256, FP32 evaluation with FP64 statistics; synthetic seeded inputs.
+Headline workload: the ragged layered batch -- 2^20 chains over 1000
+source/sensor pairs (20-degree cone sources at random depth and azimuth,
+sensors of radius 0.165 m at 10-150 m) in 100 horizontal layers of 10 m
+(scattering length log-U[10,60] m, absorption length log-U[40,250] m,
+g = 0.9), vertex cap 512, FP32 evaluation with FP64 statistics; synthetic
+seeded inputs.
 
-One benchmark step = one pass of the hot path over the batch:
-  rjpath_run_chains (1000 sampler steps for every chain: perturbation /
-  birth / death proposals, local log-density, accept, statistics)
-  + rjpath_intensity (anchor quadrature, reduction, jackknife)
-  + rjpath_grad (score pass over every path).
-The default 10 timed steps after 1 warm-up step are the workload's 10^4
-sampler steps per chain with a 10% burn-in.
+One benchmark step = one pass of the whole hot path over the batch, replayed
+from two captured graphs on one stream:
+  graph 1: rjpath_run_chains -- 1000 sampler steps of every chain
+           (perturbation / birth / death proposals, local log-density,
+           accept, statistics), launched with the autotuned configuration;
+  graph 2: rjpath_grad (score pass over every path, summed per target) and
+           rjpath_intensity_noalloc (reduction, jackknife, ESS on the device).
+Before timing: sector-tilt pilot rounds, the launch autotuner (its trial
+launches are ordinary sampler steps) and `warmup` benchmark steps of
+burn-in.  The default 10 timed steps are the workload's 10^4 sampler steps.
 
 Prints one JSON line: path-density evaluations per second (one evaluation =
-one proposal's log-density change, accepted or not), plus ESS/s of the
-detected intensity at 1% error, the roofline of the step kernel and the FP64
-oracle timed on the host cores on a bounded sample.
+one proposal whose log-density change was computed, accepted or not), the
+ESS/s of the detected intensity at 1% relative error of the median target
+(measured from the per-step intensity history), the roofline of the step
+kernel, extra measurements (the 65,536-chain homogeneous batch; the
+gradient-informed vs the plain sampler on 262,144 chains until 1% error) and
+the FP64 oracle timed on the host cores on a bounded sample.
 """
 from __future__ import annotations
 
@@ -33,20 +41,24 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP32 = 157.3e12  # MI355X published dense FP32 vector rate (FLOP/s)
 
-# Algorithmic FP32 work per proposal (FLOPs, FMA = 2, one transcendental = 1),
-# counted from the arithmetic of the method ("Roofline"):
-FLOP_PERTURB = 217.0        # Gaussian step + two segments + three turns, old and new
-FLOP_JUMP_BASE = 208.0      # mean of birth (235) and death (180): proposal, segments, turns, Jacobian
-FLOP_JUMP_PER_VERTEX = 1.0  # birth scan of the cached depths (2 per vertex over half the path, half the jumps)
+# Algorithmic FP32 work per evaluated proposal of a homogeneous medium (an
+# add, multiply, FMA or transcendental counts one):
+#  perturbation: about 130 add/mul/FMA (two segments and three turns, old and
+#    new, the Gaussian or end-point step) + about 13 transcendentals;
+#  birth / death: about 150 add/mul/FMA + 21 transcendentals, plus the birth's
+#    scan of the cached segment depths (2 per vertex).
+# Layered media add a few operations per layer crossed (not counted).
+FLOP_PERTURB = 143.0
+FLOP_JUMP_BASE = 171.0
+FLOP_JUMP_PER_VERTEX = 2.0
 
-
-# Sources of the step kernel the benchmark times (the FP32 plain-sampler
-# variant for homogeneous media); the HBM traffic recorded under profiles/ is
-# reported only while their digest matches the one recorded with it.
+# Sources of the step kernel the benchmark times (FP32, plain sampler); the HBM
+# traffic recorded under profiles/ is reported only while their digest matches
+# the one recorded with it.
 KERNEL_SOURCES = ["include/rjpath.h", "paper_1811_04156_amd/csrc/rj_internal.h",
                   "paper_1811_04156_amd/csrc/rj_device.h", "paper_1811_04156_amd/csrc/rj_step.h",
                   "paper_1811_04156_amd/csrc/rj_run.h", "paper_1811_04156_amd/csrc/rj_run_f32.hip"]
-TRAFFIC_PROFILE = "profiles/run_kernel_hom_f32_config2_traffic.md"
+TRAFFIC_PROFILE = "profiles/run_kernel_lay_f32_layered_batch_traffic.md"
 
 
 def kernel_digest() -> str:
@@ -88,94 +100,270 @@ def parse():
     ap.add_argument("--chunk", type=int, default=1000, help="sampler steps per benchmark step")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--no-extras", action="store_true", help="skip the layered and grad-vs-plain measurements")
-    ap.add_argument("--autotune", action="store_true",
-                    help="time the launch configurations first (default: the library's measured default)")
+    ap.add_argument("--no-extras", action="store_true", help="skip the homogeneous batch and grad-vs-plain legs")
+    ap.add_argument("--sampler", choices=("plain", "langevin"), default="plain",
+                    help="interior move of the headline leg (plain Gaussian step or single-vertex Langevin)")
+    ap.add_argument("--lmala-h", type=float, default=0.05,
+                    help="step-size scale of the single-vertex Langevin sampler in the grad-vs-plain leg")
+    ap.add_argument("--ess-max-steps", type=int, default=200,
+                    help="further benchmark steps allowed after the timed ones to reach 1%% error (ESS/s)")
+    ap.add_argument("--gvp-max-steps", type=int, default=1_600_000,
+                    help="sampler-step cap of each grad-vs-plain run (stops earlier at 1%% error)")
     ap.add_argument("--occupancy-probe", action="store_true",
-                    help="also time the config-2 kernel (cap 12, all paths in LDS) at one and two resident "
+                    help="also time the homogeneous step kernel (cap 12, all paths in LDS) at one and two resident "
                          "waves per SIMD (65,536 and 131,072 chains)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one plain device copy of this size (calibrates HBM byte counters)")
     return ap.parse_args()
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def evaluated(stats):
+    """Proposals whose log-density change was computed: counted steps minus
+    jumps that proposed nothing (a birth at the cap, a death at n = 2)."""
+    return float(stats[:, 0].sum() - stats[:, 15].sum())
+
+
+def flop_per_launch(stats, n_perturb, cycle_len):
+    """Algorithmic FP32 operations of the counted proposals (see FLOP_*)."""
+    nbar = stats[:, 5].sum() / max(1.0, stats[:, 0].sum())
+    perturb = float(stats[:, 6].sum())
+    jumps = float(stats[:, 7].sum() + stats[:, 8].sum() - stats[:, 15].sum())
+    return perturb * FLOP_PERTURB + jumps * (FLOP_JUMP_BASE + FLOP_JUMP_PER_VERTEX * nbar), nbar
+
+
 def cpu_baseline(w, budget_s):
     """The FP64 oracle, as it stands, on a bounded sample of the workload:
-    the first chain of every 16th chain group, sampler steps until ~budget_s."""
+    one chain from each of 16 pairs spread over the batch (the pairs' chains
+    are independent), sampler steps until ~budget_s."""
     from oracle import oracle as O
-    idx = np.arange(0, len(w["c_target"]), 256 * 16)
+    pairs = np.unique(np.asarray(w["c_target"]))[:: max(1, len(np.unique(w["c_target"])) // 16)][:16]
     ws = dict(w)
-    ws["c_target"] = np.asarray(w["c_target"])[idx]
+    ws["c_target"] = pairs.astype(np.int32)
+    ws["burn_in"] = 0
     orc = O.Oracle(ws)
     st = O.initial_state(ws)
     threads = os.cpu_count() or 1
-    steps, done, t_used = 200, 0, 0.0
+    steps, done, t_used, ev = 200, 0, 0.0, 0.0
     while t_used < budget_s:
         t0 = time.perf_counter()
-        orc.run(ws, st, steps, step0=done, threads=threads)
+        stats, _ = orc.run(ws, st, steps, step0=done, threads=threads)
         dt = time.perf_counter() - t0
         t_used += dt
         done += steps
+        ev += evaluated(stats)
         if dt < budget_s / 8:
             steps *= 2
-    evals = len(idx) * done
-    return dict(value=evals / t_used, unit="path-density evals/s", cores=min(threads, len(idx)), kind="oracle",
-                sample=f"{len(idx)} chains (one per 16 chain groups) x {done} steps, FP64, {t_used:.1f} s")
+    return dict(value=ev / t_used, unit="path-density evals/s", cores=min(threads, len(pairs)), kind="oracle",
+                cpu_model=cpu_model(), host_threads=threads,
+                sample=f"{len(pairs)} chains (one each of {len(pairs)} pairs spread over the batch) x {done} steps, "
+                       f"FP64, {t_used:.1f} s")
 
 
-def _ess_run(s, steps, chunk):
-    """Times `steps` sampler steps in chunks; returns (seconds, median se/I).
-    se/I does not depend on the anchor, so unit anchors are used."""
-    import torch
-    s._anchor = np.ones(s.T)
-    s.stats.zero_()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps // chunk):
-        s.run(chunk)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    res = s.intensity()
-    r = res["se"] / res["I"]
+def median_r(I, se):
+    r = se / I
     ok = np.isfinite(r) & (r > 0)
-    return dt, float(np.median(r[ok])) if ok.any() else float("nan"), int(ok.sum())
+    return float(np.median(r[ok])) if ok.any() else float("nan"), int(ok.sum())
 
 
-def grad_vs_plain(steps=3000, chunk=500):
-    """Config 4's layered medium and cone-source geometry (262,144 chains):
-    the plain sampler vs the gradient-informed one (joint Langevin interior
-    moves, step size tuned towards 57.4% acceptance), each after the same
-    sector-tilt tuning and burn-in; ESS/s at 1% relative error of the median
-    target, ESS/s := 1 / (r^2 t)."""
-    from paper_1811_04156_amd import tune as tuning
+def layered_headline(args):
+    import torch
     from paper_1811_04156_amd import workloads as W
     from paper_1811_04156_amd.rjpath import Sampler
+    from paper_1811_04156_amd.rjpath import LMALA, PLAIN
+    w = W.config3()
+    w.update(burn_in=0, sampler=LMALA if args.sampler == "langevin" else PLAIN, mala_h=args.lmala_h)
+    s = Sampler(w, device="cuda:0", precision="f32")
+    C = s.C
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter()
+    # untimed set-up: sector tilt (pilot rounds), launch autotuner (ordinary steps)
+    s.tune_tilt(rounds=3, steps=args.chunk)
+    block, vlds = s.autotune(2400)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t_setup
+    s.anchor()  # computed once, before capture
+    # statistics count from the first timed step on (the tuner's steps counted)
+    s.stats.zero_()
+    s.w["burn_in"] = s.step + args.warmup * args.chunk
+    g_run = s.capture_run(args.chunk)
+    g_stats, out = s.capture_stats(score=True, intensity=True, groups=16)
+    for _ in range(args.warmup):
+        s.replay(g_run)
+        g_stats.replay()
+    s.score_acc.zero_()
+    stream = torch.cuda.current_stream()
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    hist_I = torch.empty((args.steps, s.T), dtype=torch.float64, device=s.dev)
+    hist_se = torch.empty_like(hist_I)
+    e_start = ev()
+    marks = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e_start.record(stream)
+    for i in range(args.steps):
+        e0, e1, e2 = ev(), ev(), ev()
+        e0.record(stream)
+        s.replay(g_run)
+        e1.record(stream)
+        g_stats.replay()
+        hist_I[i].copy_(out["I"], non_blocking=True)
+        hist_se[i].copy_(out["se"], non_blocking=True)
+        e2.record(stream)
+        marks.append((e0, e1, e2))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms = [a.elapsed_time(b) for a, b, _ in marks]
+    t_at = [e_start.elapsed_time(c) * 1e-3 for _, _, c in marks]
+    stats = s.stats.cpu().numpy()
+    hI, hs = hist_I.cpu().numpy(), hist_se.cpu().numpy()
+    rs = [median_r(hI[i], hs[i])[0] for i in range(args.steps)]
+    hit = [i for i, r in enumerate(rs) if r <= 0.01]
+    t1, ext, extra_steps = (t_at[hit[0]], 1.0, 0) if hit else (None, None, 0)
+    # not at 1% yet: keep replaying the same two graphs (same work per step)
+    # until the median target gets there, timed from the first timed step on
+    r_last, t_last = rs[-1], t_at[-1]
+    while t1 is None and extra_steps < args.ess_max_steps:
+        for _ in range(10):
+            s.replay(g_run)
+            g_stats.replay()
+        extra_steps += 10
+        e = ev()
+        e.record(stream)
+        torch.cuda.synchronize()
+        r_last, _ = median_r(out["I"].cpu().numpy(), out["se"].cpu().numpy())
+        t_last = e_start.elapsed_time(e) * 1e-3
+        if r_last <= 0.01:
+            t1 = t_last
+    if t1 is None:
+        ext = (r_last / 0.01) ** 2
+        t1 = t_last * ext
+    elif ext is None:
+        ext = 1.0
+    evals = evaluated(stats)
+    flop, nbar = flop_per_launch(stats, w["n_perturb"], w["cycle_len"])
+    k_mean = float(np.mean(kern_ms)) * 1e-3
+    achieved = flop / args.steps / k_mean
+    acc = stats[:, 9:12].sum(0) / np.maximum(1, stats[:, 6:9].sum(0))
+    return {
+        "value": evals / wall,
+        "ms_per_step": wall / args.steps * 1e3,
+        "config": {"workload": "ragged layered batch: 2^20 chains over 1000 cone-source/sensor pairs at 10-150 m, "
+                               "100 layers x 10 m, cap 512, 1e3 sampler steps per bench step, FP32 eval / FP64 "
+                               "stats, graph-replayed hot path with the autotuned launch",
+                   "chains": C, "pairs": s.T, "layers": int(s.medium.L_total), "cap": int(w["cap"]),
+                   "sampler_steps_per_bench_step": args.chunk, "interior_move": args.sampler,
+                   "launch": {"block_chains": block, "v_lds": vlds, "graph": True}},
+        "ess_per_s": 1e4 / t1,
+        "t_1pct_s": t1,
+        "t_1pct_measured": ext == 1.0,
+        "t_1pct_extrapolation_factor": ext,
+        "t_1pct_bench_steps": (hit[0] + 1) if hit else args.steps + extra_steps,
+        "median_rel_err": rs[-1],
+        "median_rel_err_by_step": rs,
+        "mean_vertices": nbar,
+        "acceptance": {"perturb": acc[0], "birth": acc[1], "death": acc[2]},
+        "kernel_ms_per_launch": float(np.mean(kern_ms)),
+        "setup_seconds": t_setup,
+        "evaluated_fraction": evals / max(1.0, float(stats[:, 0].sum())),
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32, "traffic": recorded_traffic()},
+    }, w
+
+
+def _until_1pct(s, run, chunk, max_steps):
+    """Runs the sampler in chunks until the median target's relative error is
+    at most 1% (or max_steps); returns (steps, seconds, r).  The intensity
+    checks are part of the timed work."""
+    import torch
+    s.stats.zero_()
+    s._anchor = np.ones(s.T)  # se / I does not depend on the anchor
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done, r = 0, float("nan")
+    while done < max_steps:
+        s.run(chunk, run=run)
+        done += chunk
+        res = s.intensity()
+        r, _ = median_r(res["I"], res["se"])
+        if r <= 0.01:
+            break
+    torch.cuda.synchronize()
+    return done, time.perf_counter() - t0, r
+
+
+def grad_vs_plain(h, max_steps):
+    """262,144 chains on the layered batch's medium and cone-source geometry:
+    the plain sampler vs the single-vertex Langevin (gradient-informed)
+    sampler, each after the same sector-tilt tuning and 3000 burn-in steps,
+    run until the median target's relative error reaches 1%.
+    ESS/s := 1 / (r^2 t) at that point."""
+    from paper_1811_04156_amd import workloads as W
+    from paper_1811_04156_amd.rjpath import LMALA, PLAIN, Sampler
     out = {}
-    for name in ("plain", "mala"):
+    for name, samp in (("plain", PLAIN), ("langevin", LMALA)):
         w = W.config4()
         w.update(burn_in=0, sampler=0)
         s = Sampler(w, device="cuda:0", precision="f32")
-        tuning.tune_tilt(s, rounds=3, steps=300)
-        h = None
-        if name == "mala":
-            h, acc = tuning.tune_mala(s, h0=0.02, rounds=6, steps=150)
-        s.run(500)  # burn-in
-        dt, r, nt = _ess_run(s, steps, chunk)
+        s.tune_tilt(rounds=3, steps=300)
+        run = dict(sampler=samp, mala_h=h, burn_in=0)
+        s.run(3000, run=run)
+        steps, sec, r = _until_1pct(s, run, 4000, max_steps)
         st = s.stats.cpu().numpy()
-        out[name] = {"seconds": dt, "median_rel_err": r, "targets": nt, "ess_per_s": 1.0 / (r * r * dt),
-                     "t_1pct_s": dt * (r / 0.01) ** 2, "evals_per_s": s.C * steps / dt,
+        out[name] = {"steps": steps, "seconds": sec, "median_rel_err": r, "reached_1pct": r <= 0.01,
+                     "ess_per_s": 1.0 / (r * r * sec), "evals_per_s": evaluated(st) / sec,
+                     "perturb_acceptance": float(st[:, 9].sum() / max(1.0, st[:, 6].sum())),
                      "mean_vertices": float(st[:, 5].sum() / max(1.0, st[:, 0].sum()))}
-        if h is not None:
-            out[name].update(mala_h=h, mala_acceptance=float(st[:, 14].sum() / max(1.0, st[:, 13].sum())))
-    out["ess_ratio_mala_over_plain"] = out["mala"]["ess_per_s"] / out["plain"]["ess_per_s"]
+    out["langevin"]["mala_h"] = h
+    out["ess_ratio_langevin_over_plain"] = out["langevin"]["ess_per_s"] / out["plain"]["ess_per_s"]
     return out
 
 
+def homogeneous_batch(chunk=1000, max_steps=40_000):
+    """The 65,536-chain batch of 256 homogeneous groups (cap 256): sampler
+    throughput and time to 1% error after tilt tuning and 1000 burn-in steps."""
+    import torch
+    from paper_1811_04156_amd import workloads as W
+    from paper_1811_04156_amd.rjpath import Sampler
+    w = W.config2()
+    w["burn_in"] = 0
+    s = Sampler(w, device="cuda:0", precision="f32")
+    s.tune_tilt(rounds=3, steps=chunk)
+    s.run(chunk)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.stats.zero_()
+    e0.record(stream)
+    s.run(chunk)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    k_ms = e0.elapsed_time(e1)
+    st = s.stats.cpu().numpy()
+    flop, nbar = flop_per_launch(st, w["n_perturb"], w["cycle_len"])
+    steps, sec, r = _until_1pct(s, {}, chunk, max_steps)
+    st2 = s.stats.cpu().numpy()
+    return {"workload": "65,536 chains x 256 homogeneous groups, cap 256", "chains": s.C,
+            "evals_per_s_kernel": evaluated(st) / (k_ms * 1e-3),
+            "evals_per_s_with_checks": evaluated(st2) / sec, "kernel_ms_per_launch": k_ms,
+            "roofline_frac": flop / (k_ms * 1e-3) / PEAK_FP32, "steps_to_1pct": steps, "seconds_to_1pct": sec,
+            "median_rel_err": r, "ess_per_s": 1.0 / (r * r * sec), "mean_vertices": nbar}
+
+
 def occupancy_probe(steps=1000):
-    """The step kernel on config 2's media with cap 12 (every path fits its 12
-    LDS slots, so the work per chain-step is the same at every occupancy), at
-    one resident wave per SIMD (65,536 chains) and two (131,072 chains): how
-    much of a SIMD's issue rate one wave leaves unused."""
+    """The step kernel on the homogeneous batch's media with cap 12 (every
+    path fits its 12 LDS slots, so the work per chain-step is the same at
+    every occupancy), at one resident wave per SIMD (65,536 chains) and two
+    (131,072 chains)."""
     import torch
     from paper_1811_04156_amd import workloads as W
     from paper_1811_04156_amd.rjpath import Sampler
@@ -197,25 +385,6 @@ def occupancy_probe(steps=1000):
     return out
 
 
-def layered_throughput(steps=1000):
-    """Config 3 (2^20 chains, 100 layers, cap 512) sampler throughput."""
-    import torch
-    from paper_1811_04156_amd import workloads as W
-    from paper_1811_04156_amd.rjpath import Sampler
-    w = W.config3()
-    w["burn_in"] = 0
-    s = Sampler(w, device="cuda:0", precision="f32")
-    s.run(200)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    s.run(steps)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    st = s.stats.cpu().numpy()
-    return {"evals_per_s": s.C * steps / dt, "chains": s.C, "steps": steps,
-            "mean_vertices": float(st[:, 5].sum() / max(1.0, st[:, 0].sum()))}
-
-
 def main():
     args = parse()
     if args.gpus != 1:
@@ -223,9 +392,6 @@ def main():
               "of the chains; see DESIGN.md)", file=sys.stderr)
         sys.exit(2)
     import torch
-    from paper_1811_04156_amd import workloads as W
-    from paper_1811_04156_amd.rjpath import Sampler
-
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.copy_probe_mib:
         nb = args.copy_probe_mib << 20
@@ -234,95 +400,25 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    w = W.config2()
-    w["burn_in"] = args.warmup * args.chunk
-    from paper_1811_04156_amd import tune as tuning
-    s = Sampler(w, device="cuda:0", precision="f32")
-    stream = torch.cuda.current_stream()
-    C = s.C
-    # untimed set-up: sector tilt and launch configuration (pilot steps are
-    # ordinary sampler steps; their statistics are discarded)
-    # (the pilot rounds are full-length launches, so every dispatch of the step
-    # kernel in this program is one benchmark chunk)
-    torch.cuda.synchronize()
-    t_tune = time.perf_counter()
-    tuning.tune_tilt(s, rounds=3, steps=args.chunk)
-    block, vlds = (0, 0)
-    if args.autotune:
-        block, vlds = tuning.tune_launch(s, steps=4800)
-    torch.cuda.synchronize()
-    t_tune = time.perf_counter() - t_tune
-    s.w["burn_in"] = s.step + args.warmup * args.chunk
-    # warm-up (burn-in) steps, untimed
-    for _ in range(args.warmup):
-        s.run(args.chunk)
-        s.intensity()
-        s.grad(logp=False, score=True)
-    torch.cuda.synchronize()
-    k_ms = []
-    n_mean = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        s.run(args.chunk)
-        e1.record(stream)
-        res = s.intensity()
-        s.grad(logp=False, score=True)
-        k_ms.append((e0, e1))
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    wall = t1 - t0
-    kern = [a.elapsed_time(b) for a, b in k_ms]
-    sampler_steps = args.steps * args.chunk
-    evals = C * sampler_steps
-    value = evals / wall
-    # ESS/s of the detected intensity at 1% relative error (median target)
-    r = res["se"] / res["I"]
-    ok = np.isfinite(r) & (r > 0)
-    r_med = float(np.median(r[ok])) if ok.any() else float("nan")
-    t_sampling = wall  # statistics accumulate over the timed steps only (burn-in excluded)
-    t1pct = t_sampling * (r_med / 0.01) ** 2
-    ess_s = 1e4 / t1pct
-    # roofline of the step kernel: algorithmic FLOPs per launch / mean launch time
-    stats = s.stats.cpu().numpy()
-    nbar = stats[:, 5].sum() / max(1.0, stats[:, 0].sum())
-    mix_p = w["n_perturb"] / w["cycle_len"]
-    flop_per_prop = mix_p * FLOP_PERTURB + (1 - mix_p) * (FLOP_JUMP_BASE + FLOP_JUMP_PER_VERTEX * nbar)
-    flop_launch = flop_per_prop * C * args.chunk
-    k_mean = float(np.mean(kern)) * 1e-3
-    achieved = flop_launch / k_mean
-    acc = stats[:, 9:12].sum(0) / np.maximum(1, stats[:, 6:9].sum(0))
+    head, w = layered_headline(args)
     out = {
         "metric": "path-density evals/s + ESS/s of detected intensity at 1% err, grad vs plain",
-        "value": value,
+        "value": head.pop("value"),
         "unit": "path-density evals/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": wall / args.steps * 1e3,
+        "ms_per_step": head.pop("ms_per_step"),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "batched plain RJMCMC, 65,536 chains x 256 homogeneous groups, cap 256, "
-                               "1e4 sampler steps (1e3 per bench step), FP32 eval / FP64 stats",
-                   "chains": C, "sampler_steps_per_bench_step": args.chunk, "cap": int(w["cap"])},
-        "ess_per_s": ess_s,
-        "t_1pct_s": t1pct,
-        "median_rel_err": r_med,
-        "mean_vertices": nbar,
-        "acceptance": {"perturb": acc[0], "birth": acc[1], "death": acc[2]},
-        "kernel_ms_per_launch": float(np.mean(kern)),
-        "tuning": {"seconds": t_tune, "block_chains": block or "default (64)", "v_lds": vlds or "default (32)",
-                   "tilted_targets": int((s.logw.cpu().numpy().max(1) > 0).sum()) if s.logw is not None else 0},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32, "traffic": recorded_traffic()},
     }
+    out.update(head)
     if not args.no_extras:
-        out["layered_config3"] = layered_throughput()
-        out["grad_vs_plain"] = grad_vs_plain()
+        out["homogeneous_batch"] = homogeneous_batch()
+        out["grad_vs_plain"] = grad_vs_plain(args.lmala_h, args.gvp_max_steps)
     if args.occupancy_probe:
         out["occupancy_probe"] = occupancy_probe()
     if not args.no_cpu:

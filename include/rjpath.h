@@ -48,7 +48,9 @@ enum {
 };
 
 enum { RJPATH_F32 = 0, RJPATH_F64 = 1 };              /* element type of path vertices */
-enum { RJPATH_PLAIN = 0, RJPATH_MALA = 1 };           /* interior-vertex move */
+/* interior-vertex move: Gaussian step; joint Langevin move of all interior
+ * vertices; single-vertex Langevin move */
+enum { RJPATH_PLAIN = 0, RJPATH_MALA = 1, RJPATH_LMALA = 2 };
 enum { RJPATH_EMIT_ISO = 0, RJPATH_EMIT_VMF = 1, RJPATH_EMIT_CONE = 2 };
 enum { RJPATH_DET_UNIFORM = 0, RJPATH_DET_PAPER = 1 };
 
@@ -58,12 +60,13 @@ enum { RJPATH_DET_UNIFORM = 0, RJPATH_DET_PAPER = 1 };
  *  3 sum path length L    4 sum L^2                 5 sum n
  *  6 proposed perturb     7 proposed birth          8 proposed death
  *  9 accepted perturb    10 accepted birth         11 accepted death
- * 12 steps at n == cap   13 proposed MALA          14 accepted MALA
- * 15 reserved (0)                                                         */
+ * 12 steps at n == cap   13 proposed Langevin      14 accepted Langevin
+ * 15 jumps rejected without a density evaluation (birth at cap, death at n = 2) */
 enum { RJPATH_NSTAT = 16 };
 
 /* Per-step trace record (tests): 5 doubles per chain and step:
- * move (0 interior, 1 end point, 2 birth, 3 death, 4 MALA, 5 none),
+ * move (0 interior, 1 end point, 2 birth, 3 death, 4 joint Langevin, 5 none,
+ * 6 single-vertex Langevin),
  * accepted (0/1), index (vertex or segment, -1 if none), log A, log u. */
 enum { RJPATH_TRACE_WORDS = 5 };
 
@@ -149,8 +152,12 @@ typedef struct {
  * step0 + steps - 1; statistics accumulate for steps >= burn_in.
  * sigma: standard deviation (m) of the Gaussian interior-vertex step;
  * kappa_end: concentration of the von Mises-Fisher end-point step on the
- * sensor; sampler: RJPATH_PLAIN or RJPATH_MALA (interior steps become joint
- * Langevin moves of all interior vertices with step size mala_h, m^2).
+ * sensor; sampler: RJPATH_PLAIN; RJPATH_MALA (interior steps become joint
+ * Langevin moves of all interior vertices with step size mala_h, m^2); or
+ * RJPATH_LMALA (an interior step moves vertex j by a Langevin step
+ * y_j = f_j + (h/2) d log p / d f_j + sqrt(h) xi with the dimensionless
+ * mala_h scaling h = mala_h * min(|f_j - f_{j-1}|, |f_{j+1} - f_j|)^2; the
+ * Discussion's suggestion of gradient-informed moves).
  * block_chains (multiple of 64) and v_lds (vertex slots per chain kept in
  * LDS; each chain's LDS tile also holds two padding slots, so
  * (v_lds + 2) * block_chains vertices must fit the LDS left after the media

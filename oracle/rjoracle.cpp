@@ -581,6 +581,8 @@ void accumulate(const Ctx& cx, const Target& t, const std::vector<V3>& f, const 
     st[6 + cls] += 1;
     st[9 + cls] += rec.accepted;
     st[12] += (n == cx.cap);
+    // a jump that proposed nothing (birth at the cap, death at n = 2): no density was evaluated
+    st[15] += (rec.move == MV_BIRTH || rec.move == MV_DEATH) && rec.index < 0;
     if (rec.move == MV_MALA || rec.move == MV_LMALA) {
         st[13] += 1;
         st[14] += rec.accepted;

@@ -382,11 +382,11 @@ int check_run(const rjpath_medium* m, const rjpath_targets* t, const rjpath_chai
     if (p->n_perturb < p->cycle_len && (p->birth_thresh == 0u))
         return fail(RJPATH_EINVAL, "birth_thresh must be > 0 when jump steps are scheduled");
     if (!(p->sigma > 0) || !(p->kappa_end > 0)) return fail(RJPATH_EINVAL, "sigma and kappa_end must be > 0");
-    if (p->sampler != RJPATH_PLAIN && p->sampler != RJPATH_MALA) return fail(RJPATH_EINVAL, "bad sampler");
-    if (p->sampler == RJPATH_MALA) {
-        if (!(p->mala_h > 0)) return fail(RJPATH_EINVAL, "mala_h must be > 0");
-        if (!c->work) return fail(RJPATH_EINVAL, "the MALA sampler needs the chains' work buffer");
-    }
+    if (p->sampler != RJPATH_PLAIN && p->sampler != RJPATH_MALA && p->sampler != RJPATH_LMALA)
+        return fail(RJPATH_EINVAL, "bad sampler");
+    if (p->sampler != RJPATH_PLAIN && !(p->mala_h > 0)) return fail(RJPATH_EINVAL, "mala_h must be > 0");
+    if (p->sampler == RJPATH_MALA && !c->work)
+        return fail(RJPATH_EINVAL, "the joint Langevin sampler needs the chains' work buffer");
     if (p->block_chains != 0 && (p->block_chains % 64 != 0 || p->block_chains < 64 || p->block_chains > 256))
         return fail(RJPATH_EINVAL, "block_chains must be 64, 128, 192 or 256");
     if (p->v_lds < 0 || p->v_lds > c->cap) return fail(RJPATH_EINVAL, "v_lds must lie in [0, cap]");

@@ -177,6 +177,36 @@ template <class R> __device__ __forceinline__ LayV<R> lay_of(const Tgt<R>& T, V3
     return ly;
 }
 
+// A point's coordinate along the layer axis (FP64, absolute) and its layer
+// index, computed once per vertex and step and shared by every factor and
+// segment that touches the vertex.
+struct LPt {
+    double u;
+    int l;
+};
+
+// Layer index of axis coordinate u: for uniformly spaced edges the floor of
+// (u - e0) / h, settled against the two stored edges around it without
+// branching (the same index as layer_u).
+template <class R> __device__ __forceinline__ int layer_idx(const Tgt<R>& T, double u) {
+    const int cnt = T.mcnt;
+    if (cnt == 1) return 0;
+    if (!T.uniform) return layer_u(T, u);
+    double q = floor((u - T.e0) * T.inv_h);
+    q = fmin(fmax(q, 0.0), (double)(cnt - 1));
+    const int l = (int)q;
+    const double elo = T.edge[l], ehi = T.edge[l + 1];
+    const int up = (u >= ehi && l + 1 < cnt) ? 1 : 0;
+    const int dn = (u < elo && l > 0) ? 1 : 0;
+    return l + up - dn;
+}
+
+template <class R> __device__ __forceinline__ LPt lpt(const Tgt<R>& T, V3<R> p) {
+    if (T.mcnt == 1) return LPt{0.0, 0};
+    const double u = axis_u(T, p);
+    return LPt{u, layer_idx(T, u)};
+}
+
 // Optical depths of the segment P -> Q of length len: total c = a + b and
 // scattering b; exact piecewise integral along the layer axis (the length
 // factor of the depth definition restored).  The crossing case is done in
@@ -210,6 +240,33 @@ __device__ __forceinline__ void seg_depth(const Tgt<R>& T, V3<R> P, V3<R> Q, R l
     double inv = 1.0 / (hi - lo);
     tc = (R)(Ic * inv) * len;
     tb = (R)(Ib * inv) * len;
+}
+
+// seg_depth with the endpoints' layer points already known.
+template <class R>
+__device__ __forceinline__ void seg_depth_lp(const Tgt<R>& T, LPt P, LPt Q, R len, R& tc, R& tb) {
+    if (T.mcnt == 1) {
+        tc = T.l0.c * len;
+        tb = T.l0.b * len;
+        return;
+    }
+    // evaluated for every lane and selected (no divergent branch): inside one
+    // layer the depth is c * len; across layers the mean coefficient comes
+    // from the FP64 prefix integrals between the two axis coordinates
+    const bool swap = P.u > Q.u;
+    const double lo = swap ? Q.u : P.u, hi = swap ? P.u : Q.u;
+    const int llo = swap ? Q.l : P.l, lhi = swap ? P.l : Q.l;
+    const R* a = T.lay + llo * LY_NW;
+    const R* b = T.lay + lhi * LY_NW;
+    const R ac = a[LY_C], ab = a[LY_B];
+    const double eh = T.edge[llo + 1], el = T.edge[lhi];
+    const double2 ph = T.pre[llo + 1], pl = T.pre[lhi];
+    const double Ic = (double)ac * (eh - lo) + (pl.x - ph.x) + (double)b[LY_C] * (hi - el);
+    const double Ib = (double)ab * (eh - lo) + (pl.y - ph.y) + (double)b[LY_B] * (hi - el);
+    const bool same = P.l == Q.l;
+    const double inv = 1.0 / (same ? 1.0 : hi - lo);
+    tc = same ? ac * len : (R)(Ic * inv) * len;
+    tb = same ? ab * len : (R)(Ib * inv) * len;
 }
 
 // log of the per-steradian scattering function at a vertex with incoming and
@@ -269,6 +326,18 @@ template <class R> __device__ __forceinline__ Seg<R> make_seg(const Tgt<R>& T, V
     s.len = l2 * il;
     s.loglen = (R)0.5 * Mth<R>::log(l2);
     seg_depth(T, P, Q, s.len, s.tc, s.tb);
+    return s;
+}
+
+template <class R> __device__ __forceinline__ Seg<R> make_seg_lp(const Tgt<R>& T, V3<R> P, V3<R> Q, LPt lP, LPt lQ) {
+    Seg<R> s;
+    V3<R> r = Q - P;
+    R l2 = dot(r, r);
+    R il = Mth<R>::rsqrt(l2);
+    s.u = il * r;
+    s.len = l2 * il;
+    s.loglen = (R)0.5 * Mth<R>::log(l2);
+    seg_depth_lp(T, lP, lQ, s.len, s.tc, s.tb);
     return s;
 }
 

@@ -12,18 +12,21 @@ enum { RD_SAMPLES = 0, RD_A, RD_B, RD_L, RD_L2, RD_CHAINS, RD_NW };
 
 hipError_t launch_run(const KArgs& a, int block, hipStream_t s);
 hipError_t set_run_lds_limit();
-// the step-kernel variants of one precision and sampler (defined in rj_run.h,
+// the step-kernel variants of one precision and interior move (0 plain, 1
+// joint Langevin, 2 single-vertex Langevin; defined in rj_run.h,
 // instantiated once each in the rj_run_*.hip units)
-template <class R, bool MALA> hipError_t launch_run_v(const KArgs& a, int block, hipStream_t s);
-template <class R, bool MALA> hipError_t set_lds_limit_v();
-extern template hipError_t launch_run_v<float, false>(const KArgs&, int, hipStream_t);
-extern template hipError_t launch_run_v<float, true>(const KArgs&, int, hipStream_t);
-extern template hipError_t launch_run_v<double, false>(const KArgs&, int, hipStream_t);
-extern template hipError_t launch_run_v<double, true>(const KArgs&, int, hipStream_t);
-extern template hipError_t set_lds_limit_v<float, false>();
-extern template hipError_t set_lds_limit_v<float, true>();
-extern template hipError_t set_lds_limit_v<double, false>();
-extern template hipError_t set_lds_limit_v<double, true>();
+template <class R, int SAMP> hipError_t launch_run_v(const KArgs& a, int block, hipStream_t s);
+template <class R, int SAMP> hipError_t set_lds_limit_v();
+#define RJ_RUN_EXTERN(R, S)                                                        \
+    extern template hipError_t launch_run_v<R, S>(const KArgs&, int, hipStream_t); \
+    extern template hipError_t set_lds_limit_v<R, S>();
+RJ_RUN_EXTERN(float, 0)
+RJ_RUN_EXTERN(float, 1)
+RJ_RUN_EXTERN(float, 2)
+RJ_RUN_EXTERN(double, 0)
+RJ_RUN_EXTERN(double, 1)
+RJ_RUN_EXTERN(double, 2)
+#undef RJ_RUN_EXTERN
 hipError_t launch_grad(const KArgs& a, double* logp_out, void* dv, double* score, int L_total, hipStream_t s);
 // *counter += steps on the device (keeps captured graphs advancing)
 hipError_t launch_advance(uint64_t* counter, uint64_t steps, hipStream_t s);

@@ -2,6 +2,6 @@
 #include "rj_run.h"
 
 namespace rj {
-template hipError_t launch_run_v<float, false>(const KArgs&, int, hipStream_t);
-template hipError_t set_lds_limit_v<float, false>();
+template hipError_t launch_run_v<float, 0>(const KArgs&, int, hipStream_t);
+template hipError_t set_lds_limit_v<float, 0>();
 } // namespace rj

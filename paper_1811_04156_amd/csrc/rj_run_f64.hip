@@ -2,6 +2,6 @@
 #include "rj_run.h"
 
 namespace rj {
-template hipError_t launch_run_v<double, false>(const KArgs&, int, hipStream_t);
-template hipError_t set_lds_limit_v<double, false>();
+template hipError_t launch_run_v<double, 0>(const KArgs&, int, hipStream_t);
+template hipError_t set_lds_limit_v<double, 0>();
 } // namespace rj

@@ -118,16 +118,23 @@ __global__ void __launch_bounds__(256) grad_kernel(KArgs a, double* logp_out, Vt
 // Launchers
 // ---------------------------------------------------------------------------
 hipError_t launch_run(const KArgs& a, int block, hipStream_t s) {
-    const bool mala = a.sampler == RJPATH_MALA;
-    if (a.prec == RJPATH_F64) return mala ? launch_run_v<double, true>(a, block, s) : launch_run_v<double, false>(a, block, s);
-    return mala ? launch_run_v<float, true>(a, block, s) : launch_run_v<float, false>(a, block, s);
+    if (a.prec == RJPATH_F64) {
+        if (a.sampler == RJPATH_MALA) return launch_run_v<double, 1>(a, block, s);
+        if (a.sampler == RJPATH_LMALA) return launch_run_v<double, 2>(a, block, s);
+        return launch_run_v<double, 0>(a, block, s);
+    }
+    if (a.sampler == RJPATH_MALA) return launch_run_v<float, 1>(a, block, s);
+    if (a.sampler == RJPATH_LMALA) return launch_run_v<float, 2>(a, block, s);
+    return launch_run_v<float, 0>(a, block, s);
 }
 
 hipError_t set_run_lds_limit() {
-    hipError_t e = set_lds_limit_v<float, false>();
-    if (e == hipSuccess) e = set_lds_limit_v<float, true>();
-    if (e == hipSuccess) e = set_lds_limit_v<double, false>();
-    if (e == hipSuccess) e = set_lds_limit_v<double, true>();
+    hipError_t e = set_lds_limit_v<float, 0>();
+    if (e == hipSuccess) e = set_lds_limit_v<float, 1>();
+    if (e == hipSuccess) e = set_lds_limit_v<float, 2>();
+    if (e == hipSuccess) e = set_lds_limit_v<double, 0>();
+    if (e == hipSuccess) e = set_lds_limit_v<double, 1>();
+    if (e == hipSuccess) e = set_lds_limit_v<double, 2>();
     return e;
 }
 __global__ void advance_kernel(uint64_t* counter, uint64_t steps) {

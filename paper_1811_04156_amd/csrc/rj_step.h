@@ -30,7 +30,10 @@
 
 namespace rj {
 
-enum { MV_INTERIOR = 0, MV_END = 1, MV_BIRTH = 2, MV_DEATH = 3, MV_MALA = 4, MV_NULL = 5 };
+enum { MV_INTERIOR = 0, MV_END = 1, MV_BIRTH = 2, MV_DEATH = 3, MV_MALA = 4, MV_NULL = 5, MV_LMALA = 6 };
+
+// Interior-vertex move of the sampler (RJPATH_PLAIN / _MALA / _LMALA).
+enum { SAMP_PLAIN = 0, SAMP_JOINT = 1, SAMP_LOCAL = 2 };
 
 // Lane-private path storage: slots below V in LDS, the rest in HBM.  LO: the
 // whole path is known to be in LDS.  The LDS side is addressed through an
@@ -166,7 +169,7 @@ __device__ __forceinline__ void box_muller3(uint32_t a, uint32_t b, uint32_t c, 
 template <class R>
 __device__ __forceinline__ void seg_depth_grad(const Tgt<R>& T, V3<R> P, V3<R> Q, const Seg<R>& s, V3<R>& dP,
                                                V3<R>& dQ) {
-    R F = s.tc / s.len; // mean total coefficient along the segment
+    R F = s.tc * Mth<R>::rcp(s.len); // mean total coefficient along the segment
     dP = (-F) * s.u;
     dQ = F * s.u;
     if (T.mcnt > 1) {
@@ -184,24 +187,82 @@ __device__ __forceinline__ void seg_depth_grad(const Tgt<R>& T, V3<R> P, V3<R> Q
     }
 }
 
+// seg_depth_grad with the endpoints' layer points already known.
+template <class R>
+__device__ __forceinline__ void seg_depth_grad_lp(const Tgt<R>& T, LPt P, LPt Q, const Seg<R>& s, V3<R>& dP,
+                                                  V3<R>& dQ) {
+    R F = s.tc * Mth<R>::rcp(s.len); // mean total coefficient along the segment
+    dP = (-F) * s.u;
+    dQ = F * s.u;
+    if (T.mcnt > 1 && P.l != Q.l) {
+        double cP = (double)T.lay[P.l * LY_NW + LY_C], cQ = (double)T.lay[Q.l * LY_NW + LY_C];
+        double inv = 1.0 / (Q.u - P.u);
+        R gP = (R)((double)s.len * ((double)F - cP) * inv);
+        R gQ = (R)((double)s.len * (cQ - (double)F) * inv);
+        V3<R> ax = {(R)T.ax, (R)T.ay, (R)T.az};
+        dP = dP + gP * ax;
+        dQ = dQ + gQ * ax;
+    }
+}
+
 // d log sigma / d mu at a turn, q = |ua - ub|^2
 template <class R> __device__ __forceinline__ R dturn_dmu(const LayV<R>& ly, R q) {
     R den = ly.hg1 + ly.g * q;
-    R dhg = (R)3 * ly.g / den;
+    R dhg = (R)3 * ly.g * Mth<R>::rcp(den);
     if (ly.fsl == (R)0) return dhg;
     R hg = ly.hgn - (R)1.5 * Mth<R>::log(den);
     R v = (R)1 - (R)0.25 * q; // (1 + mu) / 2
     R sl = ly.sln + ly.sla * Mth<R>::log(v);
-    R dsl = ly.sla / ((R)2 * v);
+    R dsl = ly.sla * Mth<R>::rcp((R)2 * v);
     R m = sl > hg ? sl : hg;
     R es = ly.fsl * Mth<R>::exp(sl - m), eh = ((R)1 - ly.fsl) * Mth<R>::exp(hg - m);
-    return (es * dsl + eh * dhg) / (es + eh);
+    return (es * dsl + eh * dhg) * Mth<R>::rcp(es + eh);
 }
 
 template <class R> __device__ __forceinline__ V3<R> dunit(V3<R> u, R len, V3<R> c) {
     // d (u . c) / d r for u = r / |r|
-    R il = (R)1 / len;
+    R il = Mth<R>::rcp(len);
     return il * (c - dot(u, c) * u);
+}
+
+// Role of a vertex in a local density factor (see vtx_term).
+enum { VK_EMIT = 0, VK_TURN = 1, VK_END = 2, VK_NONE = 3 };
+
+// d log p / d f_j of an interior vertex j from its five-vertex window, the
+// terms the single-vertex evaluator reads: the segments A = f_{j-1} -> f_j and
+// B = f_j -> f_{j+1} (attenuation and inverse square), the turn at j, the turn
+// at j-1 (or, for j = 1, the emission factor, which depends on the direction
+// only for a von Mises-Fisher source), and the turn at j+1 (or the end factor
+// log(-u . nu) when f_{j+1} is the end point).  log b(f_j) is constant within
+// a layer and contributes nothing.
+template <class R>
+__device__ __forceinline__ V3<R> vertex_grad(const Tgt<R>& T, int km1, const LayV<R>& lm1, V3<R> um, LPt pm1,
+                                             LPt po, LPt pp1, const Seg<R>& A, const Seg<R>& B,
+                                             const LayV<R>& lo, int kp1, V3<R> up, V3<R> nu1, const LayV<R>& lp1) {
+    V3<R> dPA, dQA, dPB, dQB;
+    seg_depth_grad_lp(T, pm1, po, A, dPA, dQA);
+    seg_depth_grad_lp(T, po, pp1, B, dPB, dQB);
+    V3<R> g = ((R)2 * Mth<R>::rcp(B.len)) * B.u - ((R)2 * Mth<R>::rcp(A.len)) * A.u - dQA - dPB;
+    {
+        const V3<R> dd = A.u - B.u;
+        const R h = dturn_dmu(lo, dot(dd, dd));
+        g = g + h * (dunit(A.u, A.len, B.u) - dunit(B.u, B.len, A.u));
+    }
+    {
+        const V3<R> dd = um - A.u;
+        const R ht = dturn_dmu(lm1, dot(dd, dd));
+        const R he = T.ek == RJPATH_EMIT_VMF ? T.kappa : (R)0;
+        const bool turn = km1 == VK_TURN;
+        g = g + (turn ? ht : he) * dunit(A.u, A.len, turn ? um : T.ed);
+    }
+    {
+        const V3<R> dd = B.u - up;
+        const R ht = dturn_dmu(lp1, dot(dd, dd));
+        const R ce = -dot(B.u, nu1);
+        const bool turn = kp1 == VK_TURN;
+        g = g + (turn ? -ht : Mth<R>::rcp(ce)) * dunit(B.u, B.len, turn ? up : nu1);
+    }
+    return g;
 }
 
 // The streaming score as a walker fed one vertex at a time, so that two
@@ -237,7 +298,7 @@ template <class R> struct ScoreWalker {
         lp += (double)seg_term(s);
         V3<R> dP, dQ;
         seg_depth_grad(T, fprev, fcur, s, dP, dQ);
-        R il2 = (R)2 / s.len;
+        R il2 = (R)2 * Mth<R>::rcp(s.len);
         gB = gB - dP + il2 * s.u;
         const V3<R> z = {(R)0, (R)0, (R)0};
         V3<R> gC = z - dQ - il2 * s.u; // vertex k
@@ -279,7 +340,7 @@ template <class R> struct ScoreWalker {
         R idn = Mth<R>::rsqrt(dn2);
         V3<R> nu = idn * d;
         R c = -dot(uprev, nu);
-        R ic = (R)1 / c;
+        R ic = Mth<R>::rcp(c);
         V3<R> dcr = (R)-1 * dunit(uprev, lprev, nu);
         V3<R> dcd = (R)-1 * dunit(nu, dn2 * idn, uprev);
         gA = gA - ic * dcr;
@@ -308,20 +369,7 @@ __device__ __forceinline__ double score_stream(const Tgt<R>& T, const P& ps, int
     return lp;
 }
 
-// ---------------------------------------------------------------------------
-// One factor of the path density attached to one vertex (App. "Path
-// probability distribution"), evaluated branch-free so that lanes of a wave
-// whose vertices play different roles do not diverge:
-//   VK_EMIT: the source, log eps(ub) of the first direction;
-//   VK_TURN: an interior vertex, log b + log sigma_sr(ua . ub);
-//   VK_END:  the end point with outward sensor normal nu, log max(0, -ua . nu)
-//            (the angular response log rho(nu) is added by the caller where
-//            it does not cancel);
-//   VK_NONE: no vertex (0).
-// CE / CT / CN: whether the kinds END / EMIT / NONE can occur at the call.
-// ---------------------------------------------------------------------------
-enum { VK_EMIT = 0, VK_TURN = 1, VK_END = 2, VK_NONE = 3 };
-
+// Per-lane constants of the step kernel.
 struct StepCtx {
     uint32_t chain, k0, k1;
     int cap;
@@ -345,6 +393,18 @@ template <class R> __device__ __forceinline__ R rho_log(const Tgt<R>& T, V3<R> n
     return (R)3 * cr - (R)1 - (az + Mth<R>::log1p(Mth<R>::exp((R)-2 * az)) - (R)0.69314718055994530942);
 }
 
+// ---------------------------------------------------------------------------
+// One factor of the path density attached to one vertex (App. "Path
+// probability distribution"), evaluated branch-free so that lanes of a wave
+// whose vertices play different roles do not diverge:
+//   VK_EMIT: the source, log eps(ub) of the first direction;
+//   VK_TURN: an interior vertex, log b + log sigma_sr(ua . ub);
+//   VK_END:  the end point with outward sensor normal nu, log max(0, -ua . nu)
+//            (the angular response log rho(nu) is added by the caller where
+//            it does not cancel);
+//   VK_NONE: no vertex (0).
+// CE / CT / CN: whether the kinds END / EMIT / NONE can occur at the call.
+// ---------------------------------------------------------------------------
 template <class R, bool CE, bool CT, bool CN>
 __device__ __forceinline__ R vtx_term(const Tgt<R>& T, int kind, const LayV<R>& ly, V3<R> ua, V3<R> ub, V3<R> nu) {
     V3<R> d = ua - ub;
@@ -398,6 +458,7 @@ template <class R> struct Lane {
     double a1, a2, sl, sl2;
     uint64_t sn;
     uint32_t cnt, c2, ncap, pp, pb, pd, ap, ab, ad, mp, ma;
+    uint32_t ne; // jump proposals rejected without a density evaluation (birth at cap, death at n = 2)
 };
 
 template <class R> __device__ __forceinline__ void fold_run(Lane<R>& ln, int n0, int cap, bool tilt) {
@@ -423,7 +484,7 @@ template <class R> __device__ __forceinline__ void fold_hist(Lane<R>& ln, const 
 
 
 // One step of one lane; returns the move kind, writes log A / accepted / index.
-template <class R, bool LO, bool MALA>
+template <class R, bool LO, int SAMP>
 __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>& ps, const GlobalPath<R>& work,
                                           Lane<R>& ln, const StepCtx& sc, uint64_t step, bool perturb, int& move,
                                           int& idx, int& accepted, R& logA, R& logu) {
@@ -441,6 +502,7 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
         const int j = 1 + pick(r[0], (uint32_t)(n - 1));
         idx = j;
         const bool is_end = (j == n - 1);
+        constexpr bool MALA = SAMP == SAMP_JOINT;
         if (MALA && !is_end) {
             // ---------- joint Langevin move of all interior vertices ----------
             move = MV_MALA;
@@ -524,6 +586,14 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
         const V3<R> fp1 = hp1 ? gp1 : fo + ex;
         const V3<R> fp2 = hp2 ? gp2 : fp1 + ex;
         move = is_end ? MV_END : MV_INTERIOR;
+        // layer points of the window vertices, once each
+        const LPt pm1 = lpt(T, fm1), po = lpt(T, fo), pp1 = lpt(T, fp1);
+        const Seg<R> Ao = make_seg_lp(T, fm1, fo, pm1, po), Bo = make_seg_lp(T, fo, fp1, po, pp1);
+        const V3<R> um = unit_dir(fm2, fm1), up = unit_dir(fp1, fp2), nu1 = unit_dir_eta(T, fp1);
+        const LayV<R> lm1 = lay_at(T, pm1.l), lo = lay_at(T, po.l), lp1 = lay_at(T, pp1.l);
+        const int km1 = hm2 ? VK_TURN : VK_EMIT;
+        const int kj = is_end ? VK_END : VK_TURN;
+        const int kp1 = !hp1 ? VK_NONE : (hp2 ? VK_TURN : VK_END);
         // one log and one sin/cos pair serve both proposals: Box-Muller on
         // words 4..7 for the Gaussian step, and words 4, 5 for the end-point
         // von Mises-Fisher step (inverse CDF of its cosine, uniform azimuth)
@@ -531,11 +601,22 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
         const R lg = Mth<R>::log(is_end ? u4 + ((R)1 - u4) * (R)sc.e2k : u4);
         const R c5 = Mth<R>::cos2pi(u5), s5 = Mth<R>::sin2pi(u5);
         V3<R> fn, nu, nn;
+        R hx = (R)0, half_xi2 = (R)0;
         {
             const R rho1 = Mth<R>::sqrt((R)-2 * lg);
             const R rho2 = Mth<R>::sqrt((R)-2 * Mth<R>::log(unif<R>(r[6])));
             const V3<R> xi = {rho1 * c5, rho1 * s5, rho2 * Mth<R>::cos2pi(unif<R>(r[7]))};
-            const V3<R> fg = fo + (R)sc.sigma * xi;
+            V3<R> fg;
+            if constexpr (SAMP == SAMP_LOCAL) {
+                // single-vertex Langevin step with h = mala_h * (shorter adjacent segment)^2
+                const V3<R> gx = vertex_grad(T, km1, lm1, um, pm1, po, pp1, Ao, Bo, lo, kp1, up, nu1, lp1);
+                const R m = fmin(Ao.len, Bo.len);
+                hx = (R)sc.mala_h * m * m;
+                half_xi2 = (R)0.5 * dot(xi, xi);
+                fg = fo + ((R)0.5 * hx) * gx + Mth<R>::sqrt(hx) * xi;
+            } else {
+                fg = fo + (R)sc.sigma * xi;
+            }
             V3<R> dd = from_eta(T, fo), e2, e3;
             nu = Mth<R>::rsqrt(dot(dd, dd)) * dd; // sensor normal at the current end point
             onb(nu, e2, e3);
@@ -545,13 +626,9 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
             nn = wv * nu + sw * (c5 * e2 + s5 * e3); // sensor normal at the proposed end point
             fn = is_end ? T.eta + (T.eta_lo + T.rad * nn) : fg;
         }
-        const Seg<R> Ao = make_seg(T, fm1, fo), An = make_seg(T, fm1, fn);
-        const Seg<R> Bo = make_seg(T, fo, fp1), Bn = make_seg(T, fn, fp1);
-        const V3<R> um = unit_dir(fm2, fm1), up = unit_dir(fp1, fp2), nu1 = unit_dir_eta(T, fp1);
-        const LayV<R> lm1 = lay_of(T, fm1), lo = lay_of(T, fo), lnw = lay_of(T, fn), lp1 = lay_of(T, fp1);
-        const int km1 = hm2 ? VK_TURN : VK_EMIT;
-        const int kj = is_end ? VK_END : VK_TURN;
-        const int kp1 = !hp1 ? VK_NONE : (hp2 ? VK_TURN : VK_END);
+        const LPt pn = lpt(T, fn);
+        const Seg<R> An = make_seg_lp(T, fm1, fn, pm1, pn), Bn = make_seg_lp(T, fn, fp1, pn, pp1);
+        const LayV<R> lnw = lay_at(T, pn.l);
         R d = seg_term(An) - seg_term(Ao);
         d += hp1 ? seg_term(Bn) - seg_term(Bo) : (R)0;
         d += vtx_term<R, false, true, false>(T, km1, lm1, um, An.u, nu1) -
@@ -560,6 +637,17 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
              vtx_term<R, true, false, false>(T, kj, lo, Ao.u, Bo.u, nu);
         d += vtx_term<R, true, false, true>(T, kp1, lp1, Bn.u, up, nu1) -
              vtx_term<R, true, false, true>(T, kp1, lp1, Bo.u, up, nu1);
+        if constexpr (SAMP == SAMP_LOCAL) {
+            // log q(x | y) - log q(y | x) of the two Gaussian proposals, each
+            // with its own step size (so the normalisations h^{-3/2} enter)
+            const V3<R> gy = vertex_grad(T, km1, lm1, um, pm1, pn, pp1, An, Bn, lnw, kp1, up, nu1, lp1);
+            const R m = fmin(An.len, Bn.len);
+            const R hy = (R)sc.mala_h * m * m;
+            const V3<R> b = (fo - fn) - ((R)0.5 * hy) * gy;
+            const R lq = (R)1.5 * Mth<R>::log(hx * Mth<R>::rcp(hy)) - dot(b, b) * Mth<R>::rcp((R)2 * hy) + half_xi2;
+            d += is_end ? (R)0 : lq;
+            move = is_end ? MV_END : MV_LMALA;
+        }
         // the angular response changes only when the end point itself moves
         if (T.dk == RJPATH_DET_PAPER && is_end) d += rho_log(T, nn) - rho_log(T, nu);
         logA = d;
@@ -581,7 +669,7 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
     // (16 cover all but rare long paths of the batched workloads; the FP64
     // and Langevin variants keep 8 so that their registers still allow two
     // resident waves per SIMD where they did)
-    constexpr int WB = (sizeof(R) == 4 && !MALA) ? 16 : 8;
+    constexpr int WB = (sizeof(R) == 4 && SAMP == SAMP_PLAIN) ? 16 : 8;
     R wv[WB];
 #pragma unroll
     for (int v = 0; v < WB; ++v) wv[v] = ps.w(v < n - 1 ? v : 0);
@@ -639,7 +727,8 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
     }
     const V3<R> fprev = hprev ? gprev : A - ex;
     const V3<R> fnext = hnext ? gnext : B + ex;
-    const Seg<R> AB = make_seg(T, A, B);
+    const LPt pA = lpt(T, A), pB = lpt(T, B);
+    const Seg<R> AB = make_seg_lp(T, A, B, pA, pB);
     const V3<R> mid = (R)0.5 * (A + B);
     const LayV<R> lm = lay_of(T, mid);
     const R gam = (R)0.5 * AB.len;
@@ -660,9 +749,10 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
         const V3<R> fb = mid + sc_ * ((a5 - b5) * AB.u + (ab2 * ss) * tr);
         fv = birth ? fb : fj;
     }
-    const Seg<R> sA = make_seg(T, A, fv), sB = make_seg(T, fv, B);
+    const LPt pv = lpt(T, fv);
+    const Seg<R> sA = make_seg_lp(T, A, fv, pA, pv), sB = make_seg_lp(T, fv, B, pv, pB);
     const V3<R> up = unit_dir(fprev, A), un = unit_dir(B, fnext), nuB = unit_dir_eta(T, B);
-    const LayV<R> la = lay_of(T, A), lb = lay_of(T, B), lv = lay_of(T, fv);
+    const LayV<R> la = lay_at(T, pA.l), lb = lay_at(T, pB.l), lv = lay_at(T, pv.l);
     const int kA = hprev ? VK_TURN : VK_EMIT, kB = hnext ? VK_TURN : VK_END;
     // (an end point B is the same in x and y: its angular response cancels)
     const R tx = vtx_term<R, false, true, false>(T, kA, la, up, AB.u, nuB) +
@@ -720,7 +810,7 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
 
 // One sampler step of a lane inside the step loop: the move, then the move
 // counts, the per-step sums, the optional histogram and trace.
-template <class R, bool LO, bool MALA>
+template <class R, bool LO, int SAMP>
 __device__ __forceinline__ void one_step(const KArgs& a, const Tgt<R>& T, const PathRef<R, LO>& ps,
                                          const GlobalPath<R>& work, Lane<R>& ln, const StepCtx& sc, uint64_t step0,
                                          int s, int& phase, int c, int t) {
@@ -729,13 +819,14 @@ __device__ __forceinline__ void one_step(const KArgs& a, const Tgt<R>& T, const 
     int move, idx, accepted;
     R logA, logu;
     const bool counted = (int64_t)step >= a.burn_in;
-    step_body<R, LO, MALA>(T, ps, work, ln, sc, step, perturb, move, idx, accepted, logA, logu);
+    step_body<R, LO, SAMP>(T, ps, work, ln, sc, step, perturb, move, idx, accepted, logA, logu);
     {
         // move counts, branch-free (per-branch updates get merged by the
         // compiler into a dynamically indexed stack slot)
         const uint32_t cu = counted ? 1u : 0u, ca = (uint32_t)accepted;
         const uint32_t ib = cu & (move == MV_BIRTH ? 1u : 0u), id = cu & (move == MV_DEATH ? 1u : 0u);
-        const uint32_t ip = cu - ib - id, im = cu & (move == MV_MALA ? 1u : 0u);
+        const uint32_t ip = cu - ib - id, im = cu & ((move == MV_MALA || move == MV_LMALA) ? 1u : 0u);
+        ln.ne += cu & (((move == MV_BIRTH || move == MV_DEATH) && idx < 0) ? 1u : 0u);
         ln.pb += ib;
         ln.pd += id;
         ln.pp += ip;
@@ -769,7 +860,7 @@ __device__ __forceinline__ void one_step(const KArgs& a, const Tgt<R>& T, const 
 // ---------------------------------------------------------------------------
 enum { MK_HOM = 0, MK_LAY = 1, MK_LAY_LDS = 2 };
 
-template <class R, int MK, bool MALA, bool SL>
+template <class R, int MK, int SAMP, bool SL>
 __global__ void __launch_bounds__(256) run_kernel(KArgs a) {
     constexpr bool TAB = MK == MK_LAY_LDS;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -855,9 +946,9 @@ __global__ void __launch_bounds__(256) run_kernel(KArgs a) {
     int s = 0;
     while (s < a.steps) {
         for (; s < a.steps && __all(ln.n < a.V); ++s)
-            one_step<R, true, MALA>(a, T, pl, work, ln, sc, step0, s, phase, c, t);
+            one_step<R, true, SAMP>(a, T, pl, work, ln, sc, step0, s, phase, c, t);
         for (; s < a.steps && !__all(ln.n < a.V); ++s)
-            one_step<R, false, MALA>(a, T, ps, work, ln, sc, step0, s, phase, c, t);
+            one_step<R, false, SAMP>(a, T, ps, work, ln, sc, step0, s, phase, c, t);
     }
 
     fold_run(ln, T.n0, cap, sc.logw != nullptr);
@@ -887,6 +978,7 @@ __global__ void __launch_bounds__(256) run_kernel(KArgs a) {
         sp[12] += ln.ncap;
         sp[13] += ln.mp;
         sp[14] += ln.ma;
+        sp[15] += ln.ne;
     }
 }
 

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "librjpath.so")
 
 RJPATH_OK, RJPATH_EINVAL, RJPATH_ENOMEM, RJPATH_EHIP, RJPATH_ENODATA, RJPATH_ENOTSUP = 0, -1, -2, -3, -4, -5
 F32, F64 = 0, 1
-PLAIN, MALA = 0, 1
+PLAIN, MALA, LMALA = 0, 1, 2
 NSTAT = 16
 TRACE_WORDS = 5
 
@@ -219,30 +219,75 @@ class Sampler:
                          float(r["kappa_end"]), int(r.get("sampler", 0)), float(r.get("mala_h", 0.05)), int(block),
                          int(v_lds), int(chunk), _tp(trace), _tp(hist), _tp(counter))
 
-    def capture(self, steps, run=None, score=True, block=0, v_lds=0):
-        """Captures one chunk of the hot path (`steps` sampler steps, then the
-        score pass) in a CUDA/HIP graph whose every replay advances the chains
-        by `steps` steps (the step index lives in a device counter).  Returns
-        (graph, score tensor accumulated by each replay)."""
-        self.counter = torch.tensor([self.step], dtype=torch.int64, device=self.dev)
-        self.score_acc = torch.zeros((self.T, 1 + 3 * self.medium.L_total), dtype=torch.float64, device=self.dev)
-        p = self._params(steps, run, None, None, block, v_lds, 0, counter=self.counter)
+    def _capture(self, fn):
         g = torch.cuda.CUDAGraph()
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(side):
             with torch.cuda.graph(g, stream=side):
-                sp = _p(side.cuda_stream)
-                tg, ch = self._targets(), self._chains()
-                _check(load().rjpath_run_chains(self.medium.h, C.byref(tg), C.byref(ch), C.byref(p), sp))
-                if score:
-                    _check(load().rjpath_grad(self.medium.h, C.byref(tg), C.byref(ch), None, None,
-                                              _tp(self.score_acc), sp))
+                fn(_p(side.cuda_stream))
         torch.cuda.current_stream().wait_stream(side)
+        return g
+
+    def capture_run(self, steps, run=None, block=0, v_lds=0):
+        """Captures `steps` sampler steps of every chain in a CUDA/HIP graph
+        whose every replay advances the chains by `steps` steps (the step
+        index lives in a device counter).  Replay with replay_run()."""
+        self.counter = torch.tensor([self.step], dtype=torch.int64, device=self.dev)
+        p = self._params(steps, run, None, None, block, v_lds, 0, counter=self.counter)
+        tg, ch = self._targets(), self._chains()
+
+        def body(sp):
+            _check(load().rjpath_run_chains(self.medium.h, C.byref(tg), C.byref(ch), C.byref(p), sp))
+
+        g = self._capture(body)
+        self._graph_steps = steps
+        return g
+
+    def capture_stats(self, score=True, intensity=True, groups=16):
+        """Captures the per-chunk statistics of the hot path in a graph: the
+        score pass adding into self.score_acc (rjpath_grad) and the intensity
+        estimator into device tensors (rjpath_intensity_noalloc, with the
+        anchors computed once beforehand).  Returns the dict of output tensors
+        (I, se, ess, rhat) that every replay rewrites."""
+        self.score_acc = torch.zeros((self.T, 1 + 3 * self.medium.L_total), dtype=torch.float64, device=self.dev)
+        anc = torch.as_tensor(self.anchor(), dtype=torch.float64, device=self.dev)
+        out = {k: torch.empty(self.T, dtype=torch.float64, device=self.dev) for k in ("I", "se", "ess", "rhat")}
+        tg, ch = self._targets(), self._chains()
+
+        def body(sp):
+            if score:
+                _check(load().rjpath_grad(self.medium.h, C.byref(tg), C.byref(ch), None, None, _tp(self.score_acc),
+                                          sp))
+            if intensity:
+                _check(load().rjpath_intensity_noalloc(self.medium.h, C.byref(tg), C.byref(ch), int(groups), _tp(anc),
+                                                       _tp(out["I"]), _tp(out["se"]), _tp(out["ess"]),
+                                                       _tp(out["rhat"]), sp))
+
+        self._keep_graph_args = (tg, ch, anc)
+        return self._capture(body), out
+
+    def capture(self, steps, run=None, score=True, block=0, v_lds=0):
+        """Captures one chunk of the hot path (`steps` sampler steps, then the
+        score pass) in one graph whose every replay advances the chains by
+        `steps` steps.  Returns (graph, score tensor accumulated by each replay)."""
+        self.counter = torch.tensor([self.step], dtype=torch.int64, device=self.dev)
+        self.score_acc = torch.zeros((self.T, 1 + 3 * self.medium.L_total), dtype=torch.float64, device=self.dev)
+        p = self._params(steps, run, None, None, block, v_lds, 0, counter=self.counter)
+        tg, ch = self._targets(), self._chains()
+
+        def body(sp):
+            _check(load().rjpath_run_chains(self.medium.h, C.byref(tg), C.byref(ch), C.byref(p), sp))
+            if score:
+                _check(load().rjpath_grad(self.medium.h, C.byref(tg), C.byref(ch), None, None, _tp(self.score_acc),
+                                          sp))
+
+        g = self._capture(body)
         self._graph_steps = steps
         return g, self.score_acc
 
     def replay(self, g, times=1):
+        """Replays a graph from capture() / capture_run() (advancing the step index)."""
         for _ in range(times):
             g.replay()
         self.step += times * self._graph_steps

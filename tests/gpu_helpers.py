@@ -80,7 +80,97 @@ def _window(move, idx, n):
     return list(range(1, n)), list(range(1, n))  # joint move of every interior vertex
 
 
-def fp32_logA_bound(orc, t, x, y, move, idx):
+def _langevin_terms(orc, t, x, y, move, idx, mala_h):
+    """Magnitudes of the Gaussian proposal terms |y - x - (h/2) g(x)|^2 / 2h,
+    |x - y - (h/2) g(y)|^2 / 2h and 3/2 |log h| of a Langevin proposal, each
+    times (1 + the relative condition of its step size): their FP32 rounding
+    is relative to these magnitudes, which the log-density gradient does not
+    see."""
+    if move not in (4, 6) or y is None or not np.isfinite(orc.logp(t, y)):
+        return 0.0
+    gx = orc.grad(t, x, params=False)
+    gy = orc.grad(t, y, params=False)
+    ks = [idx] if move == 6 else range(1, len(x) - 1)
+    tot = 0.0
+
+    def step(v, k):
+        """step size at vertex k of path v and the relative FP32 condition of
+        it: h = mala_h * l^2 for the shorter adjacent segment l, whose FP32
+        length carries a relative error eps32 (|P| + |Q|) / l"""
+        if move != 6:
+            return mala_h, 0.0
+        la, lb = np.linalg.norm(v[k] - v[k - 1]), np.linalg.norm(v[k + 1] - v[k])
+        nb = k - 1 if la <= lb else k + 1
+        l = min(la, lb)
+        return mala_h * l * l, 2.0 * (np.abs(v[k]).sum() + np.abs(v[nb]).sum() + 1.0) / l
+
+    for k in ks:
+        hx, cx = step(x, k)
+        hy, cy = step(y, k)
+        a = y[k] - x[k] - 0.5 * hx * gx[k]
+        b = x[k] - y[k] - 0.5 * hy * gy[k]
+        ta, tb = a @ a / (2 * hx), b @ b / (2 * hy)
+        # b is formed from x - y in FP32, which cancels when |x - y| << |x|:
+        # relative condition of |b|^2 is 2 (|x| + |y|) / |b|
+        cb = 2.0 * (np.abs(x[k]).sum() + np.abs(y[k]).sum() + 1.0) / max(np.linalg.norm(b), 1e-30)
+        tot += ta * (1 + cx) + tb * (1 + cy + cb) + 1.5 * (abs(np.log(hx)) + abs(np.log(hy)) + cx + cy)
+    return tot
+
+
+def _langevin_logA(orc, t, x, y, ks, hfun):
+    """FP64 log A of a Langevin proposal y from x (moved vertices ks) for a
+    given y: the density ratio and both Gaussian proposal densities."""
+    lpy = orc.logp(t, y)
+    if not np.isfinite(lpy):
+        return -np.inf
+    gx, gy = orc.grad(t, x, params=False), orc.grad(t, y, params=False)
+    la = lpy - orc.logp(t, x)
+    for k in ks:
+        hx, hy = hfun(x, k), hfun(y, k)
+        a = y[k] - x[k] - 0.5 * hx * gx[k]
+        b = x[k] - y[k] - 0.5 * hy * gy[k]
+        la += (-1.5 * np.log(hy) - b @ b / (2 * hy)) - (-1.5 * np.log(hx) - a @ a / (2 * hx))
+    return la
+
+
+def _langevin_sensitivity(orc, t, x, y, move, idx, mala_h):
+    """Change of log A when each moved vertex of the proposal is displaced by
+    its FP32 error scale: eps32 (|y_k| + 1 m + |(h/2) g_k| (1 + c_g) + |y_k -
+    x_k|), where c_g = (|x_k| + |x_nb| + 1 m) / l_min is the relative
+    condition of the FP32 gradient (l_min the shorter adjacent segment,
+    x_nb the vertex at its other end).  The drift term dominates when h is
+    large, and then log A moves through log p(y), the reverse step size and
+    the reverse Gaussian term alike.  Maximum over four fixed sign patterns."""
+    if move not in (4, 6) or y is None or not np.isfinite(orc.logp(t, y)):
+        return 0.0
+    n = len(x)
+    ks = [idx] if move == 6 else list(range(1, n - 1))
+
+    def hfun(v, k):
+        if move != 6:
+            return mala_h
+        return mala_h * min(np.linalg.norm(v[k] - v[k - 1]), np.linalg.norm(v[k + 1] - v[k])) ** 2
+
+    gx = orc.grad(t, x, params=False)
+    dy = np.zeros_like(y)
+    for k in ks:
+        la, lb = np.linalg.norm(x[k] - x[k - 1]), np.linalg.norm(x[k + 1] - x[k])
+        nb = k - 1 if la <= lb else k + 1
+        cg = (np.abs(x[k]).sum() + np.abs(x[nb]).sum() + 1.0) / min(la, lb)
+        hx = hfun(x, k)
+        dy[k] = EPS32 * (np.abs(y[k]).sum() + 1.0 + 0.5 * hx * np.abs(gx[k]).sum() * (1 + cg)
+                         + np.abs(y[k] - x[k]).sum())
+    base = _langevin_logA(orc, t, x, y, ks, hfun)
+    rng = np.random.default_rng(0)
+    worst = 0.0
+    for _ in range(4):
+        yp = y + dy * rng.choice([-1.0, 1.0], size=y.shape)
+        v = _langevin_logA(orc, t, x, yp, ks, hfun)
+        worst = max(worst, abs(v - base) if np.isfinite(v) else np.inf)
+    return worst
+
+
+def fp32_logA_bound(orc, t, x, y, move, idx, mala_h=0.0):
     """A-priori bound of the FP32 error of one proposal's log A, computed from
     the oracle's FP64 state (never from the device's result):
     BASE_BOUND + K_BOUND * eps32 * sum over the vertices v that the local
@@ -88,7 +178,13 @@ def fp32_logA_bound(orc, t, x, y, move, idx):
     magnitude |v| carry FP32 rounding eps32 |v|, and every difference,
     direction and length the evaluation forms from them inherits it; the
     gradient turns that into log p, including the ill-conditioned short
-    segments next to a vertex (where |d log p / d v| ~ 2 / length)."""
+    segments next to a vertex (where |d log p / d v| ~ 2 / length).  For the
+    Langevin moves the magnitudes of the Gaussian proposal terms are added
+    (K_BOUND * eps32 * their sum): they can reach 1e5 when the step sizes at x
+    and y differ by orders of magnitude (log A is then hugely negative); and
+    4x the sensitivity of log A to the FP32 error of the proposal point itself
+    (_langevin_sensitivity), which the Langevin drift dominates when the step
+    size is large."""
     n = len(x)
     wx, wy = _window(move, idx, n)
     gx = orc.grad(t, x, params=False)
@@ -96,7 +192,8 @@ def fp32_logA_bound(orc, t, x, y, move, idx):
     if y is not None and np.isfinite(orc.logp(t, y)):
         gy = orc.grad(t, y, params=False)
         b += sum(np.abs(gy[k]).sum() * (np.abs(y[k]).sum() + 1.0) for k in wy)
-    return BASE_BOUND + K_BOUND * EPS32 * b
+    b += _langevin_terms(orc, t, x, y, move, idx, mala_h)
+    return BASE_BOUND + K_BOUND * EPS32 * b + 4.0 * _langevin_sensitivity(orc, t, x, y, move, idx, mala_h)
 
 
 def lockstep(rj, w, steps, burn=50, block=0, v_lds=0):
@@ -109,7 +206,7 @@ def lockstep(rj, w, steps, burn=50, block=0, v_lds=0):
     s = rj.Sampler(w, precision="f32")
     s.run(burn, block=block, v_lds=v_lds)
     out = dict(total=0, agree=0, compared=0, near=0, seg_mismatch=0, births=0, ratio=[], dA=[], n_max=0,
-               records=0)
+               records=0, worst=(0.0,))
     for _ in range(steps):
         n0, V0 = s.get_state()
         step = s.step
@@ -134,11 +231,14 @@ def lockstep(rj, w, steps, burn=50, block=0, v_lds=0):
             assert np.isfinite(g[c, 3]) == np.isfinite(rec[3]), (c, step, g[c], rec)
             bound = BASE_BOUND
             if np.isfinite(rec[3]):
-                bound = fp32_logA_bound(orc, t, x, y, int(rec[0]), int(rec[2]))
+                bound = fp32_logA_bound(orc, t, x, y, int(rec[0]), int(rec[2]), float(w.get("mala_h", 0.0)))
                 d = abs(g[c, 3] - rec[3])
                 out["compared"] += 1
                 out["dA"].append(d)
                 out["ratio"].append(d / bound)
+                if d / bound > out["worst"][0]:
+                    out["worst"] = (d / bound, c, step, int(rec[0]), int(rec[2]), float(rec[3]), float(g[c, 3]),
+                                    int(n0[c]))
             margin = bound + 1e-5
             if abs(rec[3] - rec[4]) > margin or not np.isfinite(rec[3]):
                 out["total"] += 1

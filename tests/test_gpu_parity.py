@@ -102,7 +102,7 @@ def test_fp64_free_run_matches_oracle(rj, birth_frac):
     for c in range(64):
         assert np.allclose(V[c, : n[c]], st["verts"][c, : n[c]], atol=1e-9)
     gst = s.stats.cpu().numpy()
-    counts = [0, 5, 6, 7, 8, 9, 10, 11, 12]
+    counts = [0, 5, 6, 7, 8, 9, 10, 11, 12, 15]
     assert np.array_equal(gst[:, counts], ostats[:, counts])
     # path-length sums: the device keeps L as an FP64 running sum (grouping differs)
     assert np.allclose(gst, ostats, rtol=1e-9, atol=1e-9)
@@ -139,7 +139,7 @@ def test_fp64_layered_free_run_matches_oracle(rj):
     for c in range(64):
         assert np.allclose(V[c, : n[c]], st["verts"][c, : n[c]], atol=1e-8)
     gst = s.stats.cpu().numpy()
-    counts = [0, 5, 6, 7, 8, 9, 10, 11, 12]
+    counts = [0, 5, 6, 7, 8, 9, 10, 11, 12, 15]
     assert np.array_equal(gst[:, counts], ostats[:, counts])
 
 
@@ -168,6 +168,39 @@ def test_fp64_mala_free_run_matches_oracle(rj):
     assert np.array_equal(gst[:, 13:15], ostats[:, 13:15])
 
 
+@pytest.mark.parametrize("which", ["homog", "layered"])
+def test_fp64_local_langevin_free_run_matches_oracle(rj, which):
+    """Single-vertex Langevin moves (FP64): the device's window gradient at
+    x and y, its step size and both Gaussian densities give the oracle's
+    decisions and paths step by step."""
+    if which == "homog":
+        w = W.single_target(6.0, 0.165, 8.0, 60.0, 0.9, chains=64, cap=32, burn_in=0, seed=23, sampler=2,
+                            mala_h=0.3, emit_kind=W.EMIT_VMF, emit_param=2.0, det_kind=W.DET_PAPER)
+    else:
+        w = mixed_workload(cap=32, chains=64)
+        w.update(burn_in=0, seed=29, sampler=2, mala_h=0.3)
+    steps = 800
+    s = rj.Sampler(w, precision="f64")
+    tr, _ = s.run(steps, trace=True)
+    torch.cuda.synchronize()
+    O, orc = _oracle(w)
+    st = O.initial_state(w)
+    ostats, otr = orc.run(w, st, steps, trace=True)
+    gtr = tr.cpu().numpy()
+    assert np.array_equal(gtr[..., 0], otr[..., 0])
+    assert (otr[..., 0] == 6).sum() > 3000
+    fin = np.isfinite(otr[..., 3])
+    assert np.array_equal(np.isfinite(gtr[..., 3]), fin)
+    assert np.allclose(gtr[..., 3][fin], otr[..., 3][fin], atol=1e-8, rtol=1e-9)
+    assert np.array_equal(gtr[..., 1], otr[..., 1])
+    n, V = s.get_state()
+    assert np.array_equal(n, st["n"])
+    for c in range(64):
+        assert np.allclose(V[c, : n[c]], st["verts"][c, : n[c]], atol=1e-8)
+    gst = s.stats.cpu().numpy()
+    assert np.array_equal(gst[:, 13:15], ostats[:, 13:15])
+
+
 def _lockstep_workload(which):
     if which == "homog":
         w = W.single_target(12.0, 0.165, 20.0, 80.0, 0.9, chains=64, cap=32, burn_in=0, seed=9)
@@ -180,13 +213,15 @@ def _lockstep_workload(which):
         w.update(burn_in=0, seed=13)
         return w, dict(block=64, v_lds=4, burn=400)
     w = mixed_workload(cap=32, chains=64)
-    w.update(burn_in=0, seed=6 if which == "mala" else 4)
+    w.update(burn_in=0, seed={"mala": 6, "lmala": 7}.get(which, 4))
     if which == "mala":
         w.update(sampler=1, mala_h=0.01)
+    if which == "lmala":
+        w.update(sampler=2, mala_h=0.3)
     return w, {}
 
 
-@pytest.mark.parametrize("which", ["homog", "mixed", "mala", "overflow"])
+@pytest.mark.parametrize("which", ["homog", "mixed", "mala", "lmala", "overflow"])
 def test_fp32_lockstep_replay(rj, which):
     """FP32 device steps replayed on the oracle from the device's own state:
     identical moves and proposals, |Delta log A| within the a-priori FP32
@@ -197,7 +232,8 @@ def test_fp32_lockstep_replay(rj, which):
     burn = kw.pop("burn", 50)
     r = lockstep(rj, w, steps=120 if which != "overflow" else 100, burn=burn, **kw)
     assert r["compared"] > 4000
-    assert r["ratio"].max() <= 1.0, (r["ratio"].max(), np.quantile(r["dA"], [0.5, 0.99, 1.0]))
+    # worst record: (ratio, chain, step, move, index, oracle log A, device log A, n)
+    assert r["ratio"].max() <= 1.0, (r["worst"], np.quantile(r["dA"], [0.5, 0.99, 1.0]))
     assert r["agree"] == r["total"], (r["agree"], r["total"])
     assert r["total"] > 5000
     assert r["seg_mismatch"] <= 2, r["seg_mismatch"]
@@ -205,7 +241,7 @@ def test_fp32_lockstep_replay(rj, which):
         assert r["n_max"] > 4 + 8  # paths well past the LDS slots
     print(f"{which}: {r['compared']} compared, max |dlogA| {r['dA'].max():.2e}, max ratio to bound "
           f"{r['ratio'].max():.3f}, {r['near']} near the threshold, {r['seg_mismatch']} segment mismatches, "
-          f"n_max {r['n_max']}")
+          f"n_max {r['n_max']}; worst {r['worst']}")
 
 
 def test_launch_configuration_and_resume_invariance(rj):
