@@ -61,6 +61,8 @@ def lib():
             "orc_anchor_I3": (d, [p, i, i, i, i, i, i]),
             "orc_trace": (None, [p, i, u64, i64, d, d, i, p]),
             "orc_trace_tallies": (i, []),
+            "orc_yield_map": (d, [p, i, i, i, i, p, p]),
+            "orc_yield_log_ratio": (d, [p, i, i, i, i, p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -260,6 +262,21 @@ class Oracle:
                       _ptr(tr), int(th))
         state["n"], state["verts"] = n, v
         return stats, tr
+
+    # -- relative light yield ------------------------------------------------
+    def yield_map(self, t0, t1, verts, inverse=False):
+        """The light-yield map T (or its inverse) of a path between targets t0
+        and t1; returns (mapped path, log |det dT/dx| at the sensor-0 path)."""
+        v = _f64(verts).reshape(-1, 3)
+        out = np.zeros_like(v)
+        lj = lib().orc_yield_map(self.h, int(t0), int(t1), 1 if inverse else 0, len(v), _ptr(v), _ptr(out))
+        return out, lj
+
+    def yield_log_ratio(self, t0, t1, side, verts):
+        """Bridge log-ratio of one path: log q1/q0 (side 0, a sensor-0 path)
+        or log q0/q1 at T^-1(y) (side 1, a sensor-1 path)."""
+        v = _f64(verts).reshape(-1, 3)
+        return lib().orc_yield_log_ratio(self.h, int(t0), int(t1), int(side), len(v), _ptr(v))
 
     # -- anchors and tracer -------------------------------------------------
     def anchor_I2(self, t, nv=48, npsi=48):

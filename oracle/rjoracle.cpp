@@ -843,6 +843,132 @@ double anchor_I3(const Ctx& cx, const Target& t, int nth, int nps, int nr, int n
 }
 
 // ---------------------------------------------------------------------------
+// Relative light yield (Sec. "Comparison of relative light yield", App.
+// "Relative light yield transformation").  The ratio B = I_1 / I_0 of the
+// intensities of two sensors that share a source and a medium is estimated
+// with the geometric bridge estimator
+//   B = E_0[sqrt(q_1(x) / q_0(x))] / E_1[sqrt(q_0(x) / q_1(x))],
+// q_0(x) = p_0(x), q_1(x) = p_1(T(x)) |dT/dx|, where x are paths ending on
+// sensor 0, T maps them onto paths ending on sensor 1, E_0 averages over
+// paths sampled on sensor 0 and E_1 over x = T^-1(y) for paths y sampled on
+// sensor 1.  Readings: the straight frame (m0, n0, k0) points k0 from the
+// source to sensor 0; the cylinder frame has k1 = the emission axis (the
+// cylinder's tangent at the source), m1 = minus the unit component of
+// B_hat = (eta_1 - f_0)/|.| perpendicular to k1 (the centre of curvature lies
+// at f_0 - r_C m1), n1 = k1 x m1, and m0 = the unit component of m1
+// perpendicular to k0, n0 = k0 x m0; each interior vertex goes through
+// x_bar = (f - f0).m0 / b0, y_bar = (f - f0).n0 / b0, omega = (f - f0).k0 / b0
+// to f0 - r_C m1 + (r_C + x_bar b1)(m1 cos(omega Omega) + k1 sin(omega Omega))
+// + n1 y_bar b1, whose Jacobian determinant is b1^2 Omega (r_C + x_bar b1) / b0^3
+// (the printed product is its inverse); the end point keeps its offset from
+// the sensor centre in the rotated arrival frame: nu_1 = Q nu_0 with
+// Q m0 = m1 cos(Omega) + k1 sin(Omega), Q n0 = n1, Q k0 = -m1 sin(Omega) +
+// k1 cos(Omega), scaled by the radius ratio (area factor (R1/R0)^2), which
+// keeps T a bijection.  Paths with a vertex at x_bar b1 <= -r_C or
+// |omega Omega| >= pi lie outside the map's domain: q_1 = 0 there.
+// ---------------------------------------------------------------------------
+struct YieldMap {
+    V3 m0, n0, k0, m1, n1, k1;
+    V3 eta0, eta1;
+    double b0, b1, rC, Om, R0, R1;
+    bool ok;
+};
+
+YieldMap yield_map(const Target& t0, const Target& t1) {
+    YieldMap M{};
+    M.eta0 = t0.eta;
+    M.eta1 = t1.eta;
+    M.R0 = t0.R;
+    M.R1 = t1.R;
+    double D0 = norm(t0.eta);
+    M.k0 = (1.0 / D0) * t0.eta;
+    M.b0 = D0 - t0.R;
+    V3 B = t1.eta;
+    double Bn = norm(B);
+    V3 Bh = (1.0 / Bn) * B;
+    M.k1 = t0.edir;
+    double cpsi = std::max(-1.0, std::min(1.0, dot(M.k1, Bh)));
+    V3 c = Bh - cpsi * M.k1;
+    double cn = norm(c);
+    M.ok = cn > 1e-12;
+    if (!M.ok) return M;
+    M.m1 = (-1.0 / cn) * c;
+    M.n1 = {M.k1.y * M.m1.z - M.k1.z * M.m1.y, M.k1.z * M.m1.x - M.k1.x * M.m1.z, M.k1.x * M.m1.y - M.k1.y * M.m1.x};
+    V3 m0 = M.m1 - dot(M.m1, M.k0) * M.k0;
+    double mn = norm(m0);
+    if (mn < 1e-12) {
+        onb(M.k0, &M.m0, &M.n0);
+    } else {
+        M.m0 = (1.0 / mn) * m0;
+        M.n0 = {M.k0.y * M.m0.z - M.k0.z * M.m0.y, M.k0.z * M.m0.x - M.k0.x * M.m0.z,
+                M.k0.x * M.m0.y - M.k0.y * M.m0.x};
+    }
+    double psi = std::acos(cpsi);
+    M.rC = Bn / (2.0 * std::sin(psi));
+    M.Om = 2.0 * psi - t1.R / M.rC;
+    M.b1 = M.rC * M.Om;
+    return M;
+}
+
+// T of one interior vertex; returns false outside the map's domain.
+bool yield_vertex(const YieldMap& M, V3 f, V3* out, double* logjac) {
+    double xb = dot(f, M.m0) / M.b0, yb = dot(f, M.n0) / M.b0, om = dot(f, M.k0) / M.b0;
+    double rad = M.rC + xb * M.b1, ang = om * M.Om;
+    if (!(rad > 0) || !(std::fabs(ang) < PI)) return false;
+    *out = (-M.rC) * M.m1 + rad * (std::cos(ang) * M.m1 + std::sin(ang) * M.k1) + (yb * M.b1) * M.n1;
+    *logjac += std::log(M.b1 * M.b1 * M.Om * rad / (M.b0 * M.b0 * M.b0));
+    return true;
+}
+
+// T^-1 of one interior vertex (every point off the cylinder axis has one).
+V3 yield_vertex_inv(const YieldMap& M, V3 g, double* logjac) {
+    V3 v = g + M.rC * M.m1; // relative to the centre of curvature
+    double yb = dot(v, M.n1) / M.b1;
+    double pm = dot(v, M.m1), pk = dot(v, M.k1);
+    double rad = std::sqrt(pm * pm + pk * pk), ang = std::atan2(pk, pm);
+    double xb = (rad - M.rC) / M.b1, om = ang / M.Om;
+    *logjac += std::log(M.b1 * M.b1 * M.Om * rad / (M.b0 * M.b0 * M.b0));
+    return (xb * M.b0) * M.m0 + (yb * M.b0) * M.n0 + (om * M.b0) * M.k0;
+}
+
+V3 yield_end(const YieldMap& M, V3 f, double* logjac) {
+    V3 nu = (1.0 / M.R0) * (f - M.eta0);
+    V3 r = std::cos(M.Om) * M.m1 + std::sin(M.Om) * M.k1, tg = (-std::sin(M.Om)) * M.m1 + std::cos(M.Om) * M.k1;
+    V3 nu1 = dot(nu, M.m0) * r + dot(nu, M.n0) * M.n1 + dot(nu, M.k0) * tg;
+    *logjac += 2.0 * std::log(M.R1 / M.R0);
+    return M.eta1 + M.R1 * nu1;
+}
+
+V3 yield_end_inv(const YieldMap& M, V3 g, double* logjac) {
+    V3 nu1 = (1.0 / M.R1) * (g - M.eta1);
+    V3 r = std::cos(M.Om) * M.m1 + std::sin(M.Om) * M.k1, tg = (-std::sin(M.Om)) * M.m1 + std::cos(M.Om) * M.k1;
+    V3 nu = dot(nu1, r) * M.m0 + dot(nu1, M.n1) * M.n0 + dot(nu1, tg) * M.k0;
+    *logjac += 2.0 * std::log(M.R1 / M.R0);
+    return M.eta0 + M.R0 * nu;
+}
+
+// log(q_1 / q_0) of a sensor-0 path x (side 0) or log(q_0 / q_1) at
+// x = T^-1(y) of a sensor-1 path y (side 1); -inf outside the domain.
+double yield_log_ratio(const Ctx& cx, int t0, int t1, int side, const std::vector<V3>& f) {
+    const Target &A = cx.targets[t0], &B = cx.targets[t1];
+    YieldMap M = yield_map(A, B);
+    int n = (int)f.size();
+    if (!M.ok) return NAN;
+    std::vector<V3> g(n);
+    g[0] = f[0];
+    double lj = 0.0;
+    if (side == 0) {
+        for (int k = 1; k + 1 < n; ++k)
+            if (!yield_vertex(M, f[k], &g[k], &lj)) return NEG_INF;
+        g[n - 1] = yield_end(M, f[n - 1], &lj);
+        return logp_path(cx, B, n, g.data()) + lj - logp_path(cx, A, n, f.data());
+    }
+    for (int k = 1; k + 1 < n; ++k) g[k] = yield_vertex_inv(M, f[k], &lj);
+    g[n - 1] = yield_end_inv(M, f[n - 1], &lj);
+    return logp_path(cx, A, n, g.data()) - logp_path(cx, B, n, f.data()) - lj;
+}
+
+// ---------------------------------------------------------------------------
 // Analog forward tracer (Algorithm "Ray tracer" of the appendix) with the
 // readings R10 (transparent sensor: every entry through the sensor surface
 // is scored and the photon continues) and R15 (log-weight starts at 0;
@@ -1216,5 +1342,38 @@ void orc_trace(void* h, int t, uint64_t seed, int64_t nphot, double esc, double 
 }
 
 int orc_trace_tallies(void) { return NTALLY; }
+
+// Relative light yield helpers: the map T between the paths of targets t0 and
+// t1 (kind 0: forward, 1: inverse; v / out n vertices, returns log |det| of
+// the forward map at the sensor-0 path, NaN outside its domain) and the
+// per-path bridge log-ratio (side 0: log q1/q0 of a sensor-0 path; side 1:
+// log q0/q1 of a sensor-1 path).
+double orc_yield_map(void* h, int t0, int t1, int kind, int n, const double* v, double* out) {
+    Ctx* cx = (Ctx*)h;
+    YieldMap M = yield_map(cx->targets[t0], cx->targets[t1]);
+    if (!M.ok) return NAN;
+    std::vector<V3> f(n);
+    for (int k = 0; k < n; ++k) f[k] = ld3(v + 3 * k);
+    double lj = 0.0;
+    st3(out, f[0]);
+    for (int k = 1; k + 1 < n; ++k) {
+        V3 g;
+        if (kind == 0) {
+            if (!yield_vertex(M, f[k], &g, &lj)) return NAN;
+        } else {
+            g = yield_vertex_inv(M, f[k], &lj);
+        }
+        st3(out + 3 * k, g);
+    }
+    st3(out + 3 * (n - 1), kind == 0 ? yield_end(M, f[n - 1], &lj) : yield_end_inv(M, f[n - 1], &lj));
+    return lj;
+}
+
+double orc_yield_log_ratio(void* h, int t0, int t1, int side, int n, const double* v) {
+    Ctx* cx = (Ctx*)h;
+    std::vector<V3> f(n);
+    for (int k = 0; k < n; ++k) f[k] = ld3(v + 3 * k);
+    return yield_log_ratio(*cx, t0, t1, side, f);
+}
 
 } // extern "C"

@@ -260,6 +260,84 @@ def config4(**over):
     return w
 
 
+def two_region(b1=0.3, b0=0.3, a=0.01, scale=1.0, radius=0.15, chains_per_sensor=64, cap=512, kappa=38.0,
+               steps=10_000, seed=11):
+    """The paper's synthetic test (Sec. "Implementation", Fig. setup): the
+    bulk split by the y-z plane into a region x < 0 with scattering b0 and a
+    region x >= 0 with scattering b1 (absorption a everywhere; m^-1), the
+    simplified-Liu / Henyey-Greenstein mixture with mean cosine 0.95 and
+    f_SL = 0.45, a von Mises-Fisher source (kappa = 38 along z) at the origin,
+    and two sensors of radius 0.15 m at (0, 0, 120) and (60, 7, 104) m with the
+    paper's angular response about (0, -1, 0).  `radius` may also give the two
+    radii.  `scale` multiplies the sensor positions only (0.05 gives a variant short enough for the analog tracer).
+    Target 0 is sensor 0, target 1 sensor 1; chains in two contiguous runs."""
+    media = dict(m_axis=np.array([[1.0, 0.0, 0.0]]), m_layer_off=np.array([0], np.int32),
+                 m_layer_cnt=np.array([2], np.int32), edges=np.array([-1.0, 0.0, 1.0]),
+                 lam_s=np.array([1.0 / b0, 1.0 / b1]), lam_a=np.array([1.0 / a, 1.0 / a]),
+                 g=np.array([0.95, 0.95]), f_sl=np.array([0.45, 0.45]))
+    src = np.zeros((2, 3))
+    sen = np.array([[0.0, 0.0, 120.0], [60.0, 7.0, 104.0]]) * scale
+    r = np.broadcast_to(np.asarray(radius, np.float64), (2,)).copy()
+    n, init = _straight_start(src, sen, r)
+    tg = _targets(np.zeros(2), src, sen, r, np.full(2, EMIT_VMF), np.tile([0.0, 0.0, 1.0], (2, 1)),
+                  np.full(2, kappa), n, init, np.full(2, DET_PAPER), np.tile([0.0, -1.0, 0.0], (2, 1)))
+    w = dict(name="two_region", cap=int(cap), **media, **tg,
+             c_target=np.repeat(np.arange(2, dtype=np.int32), chains_per_sensor))
+    w.update(DEFAULT_RUN)
+    w.update(seed=seed, steps=steps, burn_in=steps // 10, precision="f32")
+    return w
+
+
+def array_strings(rows=2, per_row=5, spacing=125.0, sensors=60, dz=17.0, zc=500.0):
+    """Horizontal (x, y) positions of vertical strings on a triangular lattice
+    (rows offset by half a spacing) and the sensor depths along each string."""
+    xy = np.array([[c * spacing + (r % 2) * spacing / 2, r * spacing * np.sqrt(3) / 2]
+                   for r in range(rows) for c in range(per_row)])
+    z = zc + dz * (np.arange(sensors) - (sensors - 1) / 2)
+    return xy, z
+
+
+def config5(seed=5, n_sources=50, reach=200.0, chains_per_target=512, cap=512, steps=4000, n_layers=100,
+            dz=10.0, sources=None, max_targets=None):
+    """Calibration-shaped batch: 10 vertical strings (two rows of five, 125 m
+    apart on a triangular lattice) of 60 sensors at 17 m spacing (radius
+    0.165 m) in the 100-layer medium; isotropic flasher sources at the
+    positions of n_sources sensors drawn with the seed; one target per other
+    sensor within `reach` of a source; chains_per_target chains per target in
+    contiguous runs.  The per-layer scattering and absorption lengths drawn
+    here (as for the ragged layered batch) are the ground truth of the
+    calibration fit.  `sources` (indices into the sensor list) and
+    `max_targets` cut the batch down for tests."""
+    rng = np.random.default_rng(seed)
+    lam_s = np.exp(rng.uniform(np.log(10.0), np.log(60.0), n_layers))
+    lam_a = np.exp(rng.uniform(np.log(40.0), np.log(250.0), n_layers))
+    g = np.full(n_layers, 0.9)
+    media = _layered_medium(lam_s, lam_a, g, 0.0, dz)
+    xy, z = array_strings()
+    pos = np.array([[x, y, zz] for x, y in xy for zz in z])  # (600, 3), string-major
+    src_idx = np.sort(rng.choice(len(pos), n_sources, replace=False)) if sources is None else np.asarray(sources)
+    src, sen = [], []
+    for i in src_idx:
+        d = np.linalg.norm(pos - pos[i], axis=1)
+        for k in np.nonzero((d <= reach) & (d > 0))[0]:
+            src.append(pos[i])
+            sen.append(pos[k])
+    src, sen = np.array(src), np.array(sen)
+    if max_targets is not None:
+        keep = np.argsort(np.linalg.norm(sen - src, axis=1), kind="stable")[:max_targets]
+        src, sen = src[keep], sen[keep]
+    T = len(src)
+    r = np.full(T, 0.165)
+    n, init = _straight_start(src, sen, r)
+    tg = _targets(np.zeros(T), src, sen, r, np.zeros(T, np.int32), np.tile([0, 0, 1.0], (T, 1)), np.zeros(T),
+                  n, init)
+    w = dict(name="config5", cap=int(cap), **media, **tg,
+             c_target=np.repeat(np.arange(T, dtype=np.int32), chains_per_target), t_source_sensor=src_idx)
+    w.update(DEFAULT_RUN)
+    w.update(seed=seed, steps=steps, burn_in=steps // 10, precision="f32")
+    return w
+
+
 def subset_chains(w, chains):
     """Same workload with the chain list cut to the first ``chains`` entries."""
     w = dict(w)
