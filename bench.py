@@ -14,9 +14,10 @@ from two captured graphs on one stream:
            accept, statistics), launched with the autotuned configuration;
   graph 2: rjpath_grad (score pass over every path, summed per target) and
            rjpath_intensity_noalloc (reduction, jackknife, ESS on the device).
-Before timing: sector-tilt pilot rounds, the launch autotuner (its trial
-launches are ordinary sampler steps) and `warmup` benchmark steps of
-burn-in.  The default 10 timed steps are the workload's 10^4 sampler steps.
+Before timing: sector-tilt pilot rounds, the launch autotuner and the
+proposal tuner (interior step, move mix, end-point concentration, scored by
+the intensity's ESS per second; their trials are ordinary sampler steps) and
+`warmup` benchmark steps of burn-in.  The default 10 timed steps are the workload's 10^4 sampler steps.
 
 Prints one JSON line: path-density evaluations per second (one evaluation =
 one proposal whose log-density change was computed, accepted or not), the
@@ -105,6 +106,8 @@ def parse():
                     help="interior move of the headline leg (plain Gaussian step or single-vertex Langevin)")
     ap.add_argument("--lmala-h", type=float, default=0.05,
                     help="step-size scale of the single-vertex Langevin sampler in the grad-vs-plain leg")
+    ap.add_argument("--proposal-trial", type=int, default=500,
+                    help="sampler steps per candidate and pass of the proposal tuner")
     ap.add_argument("--ess-max-steps", type=int, default=200,
                     help="further benchmark steps allowed after the timed ones to reach 1%% error (ESS/s)")
     ap.add_argument("--gvp-max-steps", type=int, default=1_600_000,
@@ -112,6 +115,10 @@ def parse():
     ap.add_argument("--occupancy-probe", action="store_true",
                     help="also time the homogeneous step kernel (cap 12, all paths in LDS) at one and two resident "
                          "waves per SIMD (65,536 and 131,072 chains)")
+    ap.add_argument("--only-homogeneous", action="store_true",
+                    help="run only the 65,536-chain homogeneous batch leg (for profiling its step kernel)")
+    ap.add_argument("--hom-max-steps", type=int, default=40_000,
+                    help="sampler-step cap of the homogeneous batch's run to 1%% error")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one plain device copy of this size (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -176,6 +183,23 @@ def median_r(I, se):
     return float(np.median(r[ok])) if ok.any() else float("nan"), int(ok.sum())
 
 
+def proposal_candidates(w, sampler):
+    """Proposal parameters the tuner tries (the workload's own first): the
+    interior step, the mix of perturbation and jump steps, the end-point
+    concentration and, for the Langevin move, its step-size scale."""
+    base = {k: w[k] for k in ("sigma", "kappa_end", "cycle_len", "n_perturb", "mala_h")}
+    out = [dict(base)]
+    for sig in (0.5, 1.0, 2.0, 4.0):
+        for npert in (2, 3):
+            out.append(dict(base, sigma=sig, cycle_len=5, n_perturb=npert))
+    for kap in (5.0, 60.0):
+        out.append(dict(base, kappa_end=kap))
+    if sampler == "langevin":
+        for h in (0.02, 0.1, 0.2):
+            out.append(dict(base, mala_h=h))
+    return out
+
+
 def layered_headline(args):
     import torch
     from paper_1811_04156_amd import workloads as W
@@ -190,6 +214,9 @@ def layered_headline(args):
     # untimed set-up: sector tilt (pilot rounds), launch autotuner (ordinary steps)
     s.tune_tilt(rounds=3, steps=args.chunk)
     block, vlds = s.autotune(2400)
+    cands = proposal_candidates(w, args.sampler)
+    best, scores = s.tune_proposal(cands, args.proposal_trial)
+    s.w.update(cands[best])
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t_setup
     s.anchor()  # computed once, before capture
@@ -263,7 +290,10 @@ def layered_headline(args):
                                "stats, graph-replayed hot path with the autotuned launch",
                    "chains": C, "pairs": s.T, "layers": int(s.medium.L_total), "cap": int(w["cap"]),
                    "sampler_steps_per_bench_step": args.chunk, "interior_move": args.sampler,
-                   "launch": {"block_chains": block, "v_lds": vlds, "graph": True}},
+                   "launch": {"block_chains": block, "v_lds": vlds, "graph": True},
+                   "proposal": {k: s.w[k] for k in ("sigma", "kappa_end", "cycle_len", "n_perturb", "mala_h")},
+                   "proposal_tuning": {"candidates": len(cands), "trial_steps": args.proposal_trial,
+                                       "best_score_over_default": float(scores[best] / scores[0])}},
         "ess_per_s": 1e4 / t1,
         "t_1pct_s": t1,
         "t_1pct_measured": ext == 1.0,
@@ -302,21 +332,22 @@ def _until_1pct(s, run, chunk, max_steps):
     return done, time.perf_counter() - t0, r
 
 
-def grad_vs_plain(h, max_steps):
+def grad_vs_plain(h, max_steps, tree_h=0.3):
     """262,144 chains on the layered batch's medium and cone-source geometry:
     the plain sampler vs the single-vertex Langevin (gradient-informed)
-    sampler, each after the same sector-tilt tuning and 3000 burn-in steps,
-    run until the median target's relative error reaches 1%.
+    sampler and the tree-coordinate sampler (a whole-path move on the first
+    step of every cycle), each after the same sector-tilt tuning and 3000
+    burn-in steps, run until the median target's relative error reaches 1%.
     ESS/s := 1 / (r^2 t) at that point."""
     from paper_1811_04156_amd import workloads as W
-    from paper_1811_04156_amd.rjpath import LMALA, PLAIN, Sampler
+    from paper_1811_04156_amd.rjpath import LMALA, PLAIN, TREE, Sampler
     out = {}
-    for name, samp in (("plain", PLAIN), ("langevin", LMALA)):
+    for name, samp, hh in (("plain", PLAIN, h), ("langevin", LMALA, h), ("tree", TREE, tree_h)):
         w = W.config4()
         w.update(burn_in=0, sampler=0)
         s = Sampler(w, device="cuda:0", precision="f32")
         s.tune_tilt(rounds=3, steps=300)
-        run = dict(sampler=samp, mala_h=h, burn_in=0)
+        run = dict(sampler=samp, mala_h=hh, burn_in=0)
         s.run(3000, run=run)
         steps, sec, r = _until_1pct(s, run, 4000, max_steps)
         st = s.stats.cpu().numpy()
@@ -325,7 +356,9 @@ def grad_vs_plain(h, max_steps):
                      "perturb_acceptance": float(st[:, 9].sum() / max(1.0, st[:, 6].sum())),
                      "mean_vertices": float(st[:, 5].sum() / max(1.0, st[:, 0].sum()))}
     out["langevin"]["mala_h"] = h
+    out["tree"]["mala_h"] = tree_h
     out["ess_ratio_langevin_over_plain"] = out["langevin"]["ess_per_s"] / out["plain"]["ess_per_s"]
+    out["ess_ratio_tree_over_plain"] = out["tree"]["ess_per_s"] / out["plain"]["ess_per_s"]
     return out
 
 
@@ -400,6 +433,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.only_homogeneous:
+        print(json.dumps({"homogeneous_batch": homogeneous_batch(max_steps=args.hom_max_steps)}), flush=True)
+        return
     head, w = layered_headline(args)
     out = {
         "metric": "path-density evals/s + ESS/s of detected intensity at 1% err, grad vs plain",
@@ -417,7 +453,7 @@ def main():
     }
     out.update(head)
     if not args.no_extras:
-        out["homogeneous_batch"] = homogeneous_batch()
+        out["homogeneous_batch"] = homogeneous_batch(max_steps=args.hom_max_steps)
         out["grad_vs_plain"] = grad_vs_plain(args.lmala_h, args.gvp_max_steps)
     if args.occupancy_probe:
         out["occupancy_probe"] = occupancy_probe()

@@ -49,8 +49,9 @@ enum {
 
 enum { RJPATH_F32 = 0, RJPATH_F64 = 1 };              /* element type of path vertices */
 /* interior-vertex move: Gaussian step; joint Langevin move of all interior
- * vertices; single-vertex Langevin move */
-enum { RJPATH_PLAIN = 0, RJPATH_MALA = 1, RJPATH_LMALA = 2 };
+ * vertices; single-vertex Langevin move; tree-coordinate move of the whole
+ * path on the first step of every cycle (Gaussian steps otherwise) */
+enum { RJPATH_PLAIN = 0, RJPATH_MALA = 1, RJPATH_LMALA = 2, RJPATH_TREE = 3 };
 enum { RJPATH_EMIT_ISO = 0, RJPATH_EMIT_VMF = 1, RJPATH_EMIT_CONE = 2 };
 enum { RJPATH_DET_UNIFORM = 0, RJPATH_DET_PAPER = 1 };
 
@@ -60,13 +61,13 @@ enum { RJPATH_DET_UNIFORM = 0, RJPATH_DET_PAPER = 1 };
  *  3 sum path length L    4 sum L^2                 5 sum n
  *  6 proposed perturb     7 proposed birth          8 proposed death
  *  9 accepted perturb    10 accepted birth         11 accepted death
- * 12 steps at n == cap   13 proposed Langevin      14 accepted Langevin
+ * 12 steps at n == cap   13 proposed Langevin or tree move   14 accepted Langevin or tree move
  * 15 jumps rejected without a density evaluation (birth at cap, death at n = 2) */
 enum { RJPATH_NSTAT = 16 };
 
 /* Per-step trace record (tests): 5 doubles per chain and step:
  * move (0 interior, 1 end point, 2 birth, 3 death, 4 joint Langevin, 5 none,
- * 6 single-vertex Langevin),
+ * 6 single-vertex Langevin, 7 tree-coordinate move of the whole path),
  * accepted (0/1), index (vertex or segment, -1 if none), log A, log u. */
 enum { RJPATH_TRACE_WORDS = 5 };
 
@@ -128,8 +129,8 @@ typedef struct {
  * are unused.  logp[c] receives log p of the final path; status[c] is 0 for a
  * healthy chain and 1 if its starting path had zero or non-finite density
  * (such a chain is not moved and adds nothing to the statistics).
- * work: MALA proposal buffer with the layout of verts (required only for
- * RJPATH_MALA, else may be NULL). */
+ * work: proposal buffer with the layout of verts (required for RJPATH_MALA
+ * and RJPATH_TREE, else may be NULL). */
 typedef struct {
     int32_t n_chains;
     int32_t cap;       /* maximum vertex count, 2 <= cap <= 4096 */
@@ -157,7 +158,14 @@ typedef struct {
  * RJPATH_LMALA (an interior step moves vertex j by a Langevin step
  * y_j = f_j + (h/2) d log p / d f_j + sqrt(h) xi with the dimensionless
  * mala_h scaling h = mala_h * min(|f_j - f_{j-1}|, |f_{j+1} - f_j|)^2; the
- * Discussion's suggestion of gradient-informed moves).
+ * Discussion's suggestion of gradient-informed moves); or RJPATH_TREE (step s
+ * with s mod cycle_len == 0 moves the whole path in the tree coordinates of
+ * App. "Path space coordinate system": the end point by the von
+ * Mises-Fisher step and every interior vertex's bi-spherical coordinates
+ * (zeta = artanh cos s, t, phi) about its foci by Gaussian steps of variance
+ * mala_h / n, Sec. "Path proposal distribution"; vertex k draws one Philox
+ * block with counter word 3 = 2 + k; the other perturbation steps are
+ * Gaussian steps sigma).
  * block_chains (multiple of 64) and v_lds (vertex slots per chain kept in
  * LDS; each chain's LDS tile also holds two padding slots, so
  * (v_lds + 2) * block_chains vertices must fit the LDS left after the media
@@ -191,6 +199,16 @@ typedef struct {
     uint32_t* hist;
     uint64_t* step_counter;
 } rjpath_run_params;
+
+/* One candidate of rjpath_tune_proposal: the proposal parameters of
+ * rjpath_run_params it replaces. */
+typedef struct {
+    double sigma;
+    double kappa_end;
+    double mala_h;
+    int32_t cycle_len;
+    int32_t n_perturb;
+} rjpath_proposal;
 
 /* Thread-local description of the last error. */
 const char* rjpath_last_error(void);
@@ -258,6 +276,54 @@ int rjpath_intensity(rjpath_medium* m, const rjpath_targets* t, const rjpath_cha
 int rjpath_intensity_noalloc(rjpath_medium* m, const rjpath_targets* t, const rjpath_chains* c, int32_t groups,
                              const double* anchor, double* I, double* se, double* ess, double* rhat, void* stream);
 
+/* Relative light yield B = I_1 / I_0 of two sensors lit by one source
+ * (Sec. "Comparison of relative light yield"), by the geometric bridge
+ * estimator  B = E_0[sqrt(q_1 / q_0)] / E_1[sqrt(q_0 / q_1)]  with
+ * q_0(x) = p_0(x) and q_1(x) = p_1(T x) |dT/dx| for paths x ending on sensor 0,
+ * where T bends a path toward sensor 1 along a cylinder tangent to the
+ * emission axis at the source (App. "Relative light yield transformation";
+ * interior vertex Jacobian b1^2 Omega (r_C + xbar b1) / b0^3, end point moved
+ * rigidly by the rotation of the arrival frames and scaled by R1 / R0).
+ * This call adds one sample per chain from the chains' current paths (a
+ * snapshot; call it between runs, e.g. every few hundred steps):
+ *  pairs  device, 2 * n_pairs targets (t0, t1): same source position, same
+ *         medium; t0's emission direction gives the cylinder's tangent
+ *  role   device, n_targets: 2 k + side for a target of pair k (side 0 for t0,
+ *         1 for t1), -1 for a target in no pair (each target in at most one pair)
+ *  acc    device, n_pairs * 2 * groups * 2 doubles, ADDED to:
+ *         acc[((k * 2 + side) * groups + g) * 2 + 0] += sqrt(r) / w(n),
+ *         acc[... + 1] += 1 / w(n) over the chains of chain group g (the
+ *         intensity estimator's hash) with status 0, where r = q_1(x) / q_0(x)
+ *         for a chain on t0 (0 where T x leaves the map's domain) and
+ *         r = q_0(x) / q_1(x) at x = T^-1 y for a chain on t1 (path y)
+ *  logr   device, n_chains doubles, or NULL: log r of each chain (NaN for
+ *         chains in no valid pair)
+ * The tilt 1/w(n) makes tilted chains estimate untilted expectations (T
+ * keeps the vertex count).  A pair whose targets differ in source or medium,
+ * or whose geometry has no cylinder (sensor 1 on the emission axis), adds
+ * nothing.  Asynchronous on `stream`; allocates nothing. */
+int rjpath_yield_accumulate(rjpath_medium* m, const rjpath_targets* t, const rjpath_chains* c, int32_t n_pairs,
+                            const int32_t* pairs, const int32_t* role, int32_t groups, double* acc, double* logr,
+                            void* stream);
+
+/* B and its standard error (delete-one-group jackknife, the group deleted on
+ * both sides) per pair from the sums of rjpath_yield_accumulate.  acc: device;
+ * B, se: host, n_pairs doubles each (either may be NULL).  Synchronises
+ * `stream`.  RJPATH_ENODATA if a pair has no samples on a side or no overlap
+ * (its outputs are NaN; the others are still written). */
+int rjpath_yield(int32_t n_pairs, int32_t groups, const double* acc, double* B, double* se, void* stream);
+
+/* Path-length histogram of the current paths per target (the arrival-time
+ * distribution at a sensor is that of L / c in a bulk of constant index;
+ * Sec. "Comparison of timing distributions"): for each chain with status 0,
+ * hist[t * (bins + 1) + b] += 1 / w(n) where b = floor((L - l0) / bin_width)
+ * lies in [0, bins), and hist[t * (bins + 1) + bins] += 1 / w(n) always, so
+ * that the normalised histogram of p is hist[t][b] / hist[t][bins].
+ * L = sum of segment lengths, summed in FP64.  hist: device,
+ * n_targets * (bins + 1) doubles, added to.  Asynchronous; allocates nothing. */
+int rjpath_length_hist(rjpath_medium* m, const rjpath_targets* t, const rjpath_chains* c, int32_t bins, double l0,
+                       double bin_width, double* hist, void* stream);
+
 /* Score of the current paths, recomputed from the vertices (no stored tape):
  *  logp_out[C]      (device, may be NULL): log p of each path, FP64 sum
  *  dlogp_dv         (device, may be NULL): d log p / d vertex, layout of verts,
@@ -310,6 +376,23 @@ int rjpath_dlogi_dtheta(rjpath_medium* m, const rjpath_targets* t, const double*
 int rjpath_autotune(rjpath_medium* m, const rjpath_targets* t, const rjpath_chains* c,
                     const rjpath_run_params* p, int32_t steps, int32_t* best_block_chains, int32_t* best_v_lds,
                     void* stream);
+
+/* Picks the proposal parameters (interior step sigma, end-point
+ * concentration kappa_end, Langevin step mala_h, and the move mix
+ * n_perturb / cycle_len) that give the intensity estimator the most effective
+ * samples per second: each candidate runs `trial_steps` ordinary sampler steps
+ * from p (two passes over the candidates, the second in reverse order, so the
+ * chains advance by 2 * n_cand * trial_steps steps from p->step0), with its
+ * statistics in a buffer of its own (c->stats is untouched); its score is
+ * 1 / (median over targets of (se / I)^2 x seconds per trial), where se / I is
+ * the jackknife relative error over `groups` chain groups of that trial's
+ * estimator ratio.  Every candidate kernel leaves the path density invariant,
+ * so the trials may serve as burn-in.  score: host, n_cand doubles or NULL;
+ * best: host, the index of the highest score.  Allocates (the trial
+ * statistics) and synchronises `stream`. */
+int rjpath_tune_proposal(rjpath_medium* m, const rjpath_targets* t, const rjpath_chains* c, const rjpath_run_params* p,
+                         int32_t n_cand, const rjpath_proposal* cand, int32_t trial_steps, int32_t groups,
+                         double* score, int32_t* best, void* stream);
 
 #ifdef __cplusplus
 }

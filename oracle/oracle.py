@@ -63,6 +63,8 @@ def lib():
             "orc_trace_tallies": (i, []),
             "orc_yield_map": (d, [p, i, i, i, i, p, p]),
             "orc_yield_log_ratio": (d, [p, i, i, i, i, p]),
+            "orc_tree_coords": (d, [i, p, p, p, p]),
+            "orc_tree_path": (d, [i, p, p, p, p, p, p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -87,6 +89,26 @@ def _i32(a):
 # ---------------------------------------------------------------------------
 # scalar helpers (closed forms of the paper)
 # ---------------------------------------------------------------------------
+def tree_coords(verts):
+    """Tree coordinates (zeta, t, phi), each (n,) by vertex index, of a path
+    and log |d path / d coordinates|."""
+    v = _f64(verts).reshape(-1, 3)
+    n = len(v)
+    z, t, ph = np.zeros(n), np.zeros(n), np.zeros(n)
+    lj = lib().orc_tree_coords(n, _ptr(v), _ptr(z), _ptr(t), _ptr(ph))
+    return z, t, ph, lj
+
+
+def tree_path(f0, fend, zeta, t, phi):
+    """The path with end points f0, fend and interior tree coordinates; returns
+    (path (n, 3), log-Jacobian)."""
+    z, tt, ph = _f64(zeta), _f64(t), _f64(phi)
+    n = len(z)
+    out = np.zeros((n, 3))
+    lj = lib().orc_tree_path(n, _ptr(_f64(f0)), _ptr(_f64(fend)), _ptr(z), _ptr(tt), _ptr(ph), _ptr(out))
+    return out, lj
+
+
 def philox(ctr, key):
     c = np.ascontiguousarray(ctr, dtype=np.uint32)
     k = np.ascontiguousarray(key, dtype=np.uint32)

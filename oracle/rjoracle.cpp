@@ -326,11 +326,12 @@ struct Params {
     int cycle_len, n_perturb;
     uint32_t birth_thresh; // birth iff draw < birth_thresh (birth fraction * 2^32)
     double sigma, kappa_end;
-    int sampler; // 0 plain, 1 joint Langevin move of all interior vertices, 2 single-vertex Langevin move
+    int sampler; // 0 plain, 1 joint Langevin move of all interior vertices, 2 single-vertex Langevin move,
+                 // 3 tree-coordinate move of the whole path (first step of every cycle)
     double mala_h;
 };
 
-enum { MV_INTERIOR = 0, MV_END = 1, MV_BIRTH = 2, MV_DEATH = 3, MV_MALA = 4, MV_NULL = 5, MV_LMALA = 6 };
+enum { MV_INTERIOR = 0, MV_END = 1, MV_BIRTH = 2, MV_DEATH = 3, MV_MALA = 4, MV_NULL = 5, MV_LMALA = 6, MV_TREE = 7 };
 enum { NSTAT = 16 };
 
 struct StepRec {
@@ -473,6 +474,157 @@ Prop propose_mala(const Ctx& cx, const Target& t, const Params& P, const std::ve
     return pr;
 }
 
+// ---------------------------------------------------------------------------
+// Tree coordinates of a path (App. "Path space coordinate system") and the
+// global move built on them (Sec. "Path proposal distribution").
+// Interval (k, l) with l - k >= 2 places vertex m = floor((k + l) / 2) by
+// bi-spherical coordinates about the foci f_k, f_l, with s replaced by
+// zeta = artanh(cos s); it then splits into (k, m) and (m, l).  The root is
+// (0, n - 1).  The azimuth phi of vertex m is measured in the frame of its
+// interval: the root's frame is the orthonormal completion of its axis
+// (onb); a child's frame is its parent's frame turned about the parent's
+// axis by the parent vertex's phi, then by the rotation that takes the
+// parent's axis to the child's.  Vertex m given its ancestors is the
+// bi-spherical map of (zeta, t, phi), so the Jacobian of the whole map is the
+// product over vertices of gamma^3 sech^2(zeta) / (cosh t - tanh zeta)^3
+// (the printed cosh^2 zeta is read as sech^2 zeta: sin s ds = sech^2 zeta dzeta).
+// ---------------------------------------------------------------------------
+struct TreeNode {
+    int k, l, m, parent; // parent: index into the node list (-1: root)
+};
+
+std::vector<TreeNode> tree_nodes(int n) {
+    std::vector<TreeNode> out;
+    std::vector<TreeNode> queue{{0, n - 1, 0, -1}};
+    for (size_t q = 0; q < queue.size(); ++q) {
+        TreeNode nd = queue[q];
+        if (nd.l - nd.k < 2) continue;
+        nd.m = (nd.k + nd.l) / 2;
+        const int me = (int)out.size();
+        out.push_back(nd);
+        queue.push_back({nd.k, nd.m, 0, me});
+        queue.push_back({nd.m, nd.l, 0, me});
+    }
+    return out;
+}
+
+struct Frame {
+    V3 e1, e2, e3;
+};
+
+V3 cross3(V3 a, V3 b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
+
+// Rodrigues rotation of v about the unit axis a by the angle with cosine c, sine s
+V3 rotate_about(V3 v, V3 a, double c, double s) { return c * v + s * cross3(a, v) + ((1 - c) * dot(a, v)) * a; }
+
+Frame child_frame(const Frame& P, double phi_p, V3 e1c) {
+    V3 e2r = std::cos(phi_p) * P.e2 + std::sin(phi_p) * P.e3;
+    V3 e3r = (-std::sin(phi_p)) * P.e2 + std::cos(phi_p) * P.e3;
+    V3 ax = cross3(P.e1, e1c);
+    double sn = norm(ax), cs = dot(P.e1, e1c);
+    if (!(sn > 0)) return {e1c, e2r, e3r};
+    ax = (1.0 / sn) * ax;
+    return {e1c, rotate_about(e2r, ax, cs, sn), rotate_about(e3r, ax, cs, sn)};
+}
+
+double tree_logjac(double gam, double zeta, double t) {
+    return 3 * std::log(gam) + 2 * std::log(1.0 / std::cosh(zeta)) - 3 * std::log(std::cosh(t) - std::tanh(zeta));
+}
+
+// Coordinates (zeta, t, phi) of every interior vertex (indexed by vertex) and
+// log |d path / d coordinates|.
+double tree_coords(const std::vector<V3>& f, std::vector<double>& zeta, std::vector<double>& tt,
+                   std::vector<double>& phi) {
+    const int n = (int)f.size();
+    zeta.assign(n, 0.0);
+    tt.assign(n, 0.0);
+    phi.assign(n, 0.0);
+    std::vector<TreeNode> nodes = tree_nodes(n);
+    std::vector<Frame> fr(nodes.size());
+    double lj = 0;
+    for (size_t i = 0; i < nodes.size(); ++i) {
+        const TreeNode& nd = nodes[i];
+        V3 A = f[nd.k], B = f[nd.l], x = f[nd.m];
+        V3 e1 = (1.0 / norm(B - A)) * (B - A);
+        if (nd.parent < 0) {
+            fr[i].e1 = e1;
+            onb(e1, &fr[i].e2, &fr[i].e3);
+        } else {
+            fr[i] = child_frame(fr[nd.parent], phi[nodes[nd.parent].m], e1);
+        }
+        double dA = norm(x - A), dB = norm(x - B);
+        double cs = std::max(-1.0, std::min(1.0, dot(A - x, B - x) / (dA * dB)));
+        zeta[nd.m] = std::atanh(cs);
+        tt[nd.m] = std::log(dA / dB);
+        V3 q = x - 0.5 * (A + B);
+        phi[nd.m] = std::atan2(dot(q, fr[i].e3), dot(q, fr[i].e2));
+        lj += tree_logjac(0.5 * norm(B - A), zeta[nd.m], tt[nd.m]);
+    }
+    return lj;
+}
+
+// The path with end points f0, fend and interior coordinates (zeta, t, phi);
+// returns log |d path / d coordinates| through *lj.
+std::vector<V3> tree_path(V3 f0, V3 fend, int n, const std::vector<double>& zeta, const std::vector<double>& tt,
+                          const std::vector<double>& phi, double* lj) {
+    std::vector<V3> f(n);
+    f[0] = f0;
+    f[n - 1] = fend;
+    std::vector<TreeNode> nodes = tree_nodes(n);
+    std::vector<Frame> fr(nodes.size());
+    *lj = 0;
+    for (size_t i = 0; i < nodes.size(); ++i) {
+        const TreeNode& nd = nodes[i];
+        V3 A = f[nd.k], B = f[nd.l];
+        V3 e1 = (1.0 / norm(B - A)) * (B - A);
+        if (nd.parent < 0) {
+            fr[i].e1 = e1;
+            onb(e1, &fr[i].e2, &fr[i].e3);
+        } else {
+            fr[i] = child_frame(fr[nd.parent], phi[nodes[nd.parent].m], e1);
+        }
+        const double gam = 0.5 * norm(B - A), z = zeta[nd.m], t = tt[nd.m], p = phi[nd.m];
+        V3 dir = std::sinh(t) * e1 + (1.0 / std::cosh(z)) * (std::cos(p) * fr[i].e2 + std::sin(p) * fr[i].e3);
+        f[nd.m] = 0.5 * (A + B) + (gam / (std::cosh(t) - std::tanh(z))) * dir;
+        *lj += tree_logjac(gam, z, t);
+    }
+    return f;
+}
+
+// The global move: the end point takes a von Mises-Fisher step on the sensor
+// (uniforms ue[0..1], as the end-point perturbation), then every interior
+// coordinate zeta, t, phi a Gaussian step of variance mala_h / n (three
+// normals per vertex k from the uniforms U[4(k-1) .. 4(k-1)+3]); the proposal
+// is symmetric in (end point, coordinates), so
+// log A = log p(y) - log p(x) + log J(y) - log J(x).
+Prop propose_tree(const Ctx& cx, const Target& t, const Params& P, const std::vector<V3>& f, const double ue[2],
+                  const double* U) {
+    const int n = (int)f.size();
+    Prop pr{MV_TREE, f, NEG_INF};
+    std::vector<double> z, tt, ph;
+    const double ljx = tree_coords(f, z, tt, ph);
+    V3 d = f[n - 1] - t.eta;
+    V3 nu = (1.0 / norm(d)) * d, e2, e3;
+    onb(nu, &e2, &e3);
+    const double k = P.kappa_end;
+    const double w = 1.0 + std::log(ue[0] + (1.0 - ue[0]) * std::exp(-2 * k)) / k;
+    const double sw = std::sqrt(std::max(0.0, 1.0 - w * w));
+    const double az = 2 * PI * ue[1];
+    V3 yend = t.eta + t.R * (w * nu + sw * (std::cos(az) * e2 + std::sin(az) * e3));
+    const double sig = std::sqrt(P.mala_h / n);
+    for (int m = 1; m <= n - 2; ++m) {
+        V3 xi = box_muller3(U + 4 * (m - 1));
+        z[m] += sig * xi.x;
+        tt[m] += sig * xi.y;
+        ph[m] += sig * xi.z;
+    }
+    double ljy = 0;
+    pr.y = tree_path(f[0], yend, n, z, tt, ph, &ljy);
+    const double lpy = logp_path(cx, t, n, pr.y.data());
+    if (std::isfinite(lpy) && std::isfinite(ljy)) pr.logA = lpy - logp_path(cx, t, n, f.data()) + ljy - ljx;
+    return pr;
+}
+
 // Birth of a vertex on segment k of f (n < cap) from the uniforms u[0..2]:
 // cos s by the inverse CDF of q(s), t = logit(u1) (logistic q(t)),
 // phi = 2 pi u2, new vertex at the bi-spherical point (s, t, phi) of the foci
@@ -519,7 +671,18 @@ StepRec rj_step(const Ctx& cx, const Target& t, const Params& P, uint32_t chain,
     bool perturb = (int)(step % (uint64_t)P.cycle_len) < P.n_perturb;
     const double u4[4] = {unif(r[4]), unif(r[5]), unif(r[6]), unif(r[7])};
     Prop pr{MV_NULL, {}, NEG_INF};
-    if (perturb) {
+    const bool tree = perturb && P.sampler == 3 && step % (uint64_t)P.cycle_len == 0;
+    if (tree) {
+        rec.index = -1;
+        uint32_t key[2] = {(uint32_t)P.seed, (uint32_t)(P.seed >> 32)};
+        std::vector<double> U(4 * std::max(0, n - 2));
+        for (int k = 1; k <= n - 2; ++k) {
+            uint32_t c[4] = {chain, (uint32_t)step, (uint32_t)(step >> 32), 2u + (uint32_t)k}, q[4];
+            philox4x32_10(c, key, q);
+            for (int i = 0; i < 4; ++i) U[4 * (k - 1) + i] = unif(q[i]);
+        }
+        pr = propose_tree(cx, t, P, f, u4, U.data());
+    } else if (perturb) {
         int j = 1 + (int)pick(r[0], (uint32_t)(n - 1));
         rec.index = j;
         if (j <= n - 2 && P.sampler == 1) {
@@ -576,14 +739,16 @@ void accumulate(const Ctx& cx, const Target& t, const std::vector<V3>& f, const 
     st[3] += L;
     st[4] += L * L;
     st[5] += n;
-    int cls = (rec.move == MV_INTERIOR || rec.move == MV_END || rec.move == MV_MALA || rec.move == MV_LMALA) ? 0
-              : (rec.move == MV_BIRTH ? 1 : 2);
+    int cls = (rec.move == MV_INTERIOR || rec.move == MV_END || rec.move == MV_MALA || rec.move == MV_LMALA ||
+               rec.move == MV_TREE)
+                  ? 0
+                  : (rec.move == MV_BIRTH ? 1 : 2);
     st[6 + cls] += 1;
     st[9 + cls] += rec.accepted;
     st[12] += (n == cx.cap);
     // a jump that proposed nothing (birth at the cap, death at n = 2): no density was evaluated
     st[15] += (rec.move == MV_BIRTH || rec.move == MV_DEATH) && rec.index < 0;
-    if (rec.move == MV_MALA || rec.move == MV_LMALA) {
+    if (rec.move == MV_MALA || rec.move == MV_LMALA || rec.move == MV_TREE) {
         st[13] += 1;
         st[14] += rec.accepted;
     }
@@ -1255,11 +1420,38 @@ double orc_propose(void* h, const uint64_t* ip, const double* dp, int t, int kin
     if (kind == 0) pr = propose_perturb(*cx, tg, P, f, idx, u);
     else if (kind == 1) pr = propose_birth(*cx, tg, P, f, idx, u);
     else if (kind == 2) pr = propose_death(*cx, tg, P, f, idx);
-    else pr = propose_mala(*cx, tg, P, f, u);
+    else if (kind == 3) pr = propose_mala(*cx, tg, P, f, u);
+    else pr = propose_tree(*cx, tg, P, f, u, u + 2);
     *ny = (int)pr.y.size();
     for (int k = 0; k < *ny; ++k) st3(y + 3 * k, pr.y[k]);
     *move = pr.move;
     return pr.logA;
+}
+
+// Tree coordinates of a path (n vertices at v): zeta, t, phi (n each, by
+// vertex index; 0 at the end points); returns log |d path / d coordinates|.
+double orc_tree_coords(int n, const double* v, double* zeta, double* t, double* phi) {
+    std::vector<V3> f(n);
+    for (int k = 0; k < n; ++k) f[k] = ld3(v + 3 * k);
+    std::vector<double> z, tt, ph;
+    double lj = tree_coords(f, z, tt, ph);
+    for (int k = 0; k < n; ++k) {
+        zeta[k] = z[k];
+        t[k] = tt[k];
+        phi[k] = ph[k];
+    }
+    return lj;
+}
+
+// The path of n vertices with end points f0, fend and interior coordinates
+// (zeta, t, phi by vertex index) into out (3n); returns the log-Jacobian.
+double orc_tree_path(int n, const double* f0, const double* fend, const double* zeta, const double* t,
+                     const double* phi, double* out) {
+    std::vector<double> z(zeta, zeta + n), tt(t, t + n), ph(phi, phi + n);
+    double lj = 0;
+    std::vector<V3> f = tree_path(ld3(f0), ld3(fend), n, z, tt, ph, &lj);
+    for (int k = 0; k < n; ++k) st3(out + 3 * k, f[k]);
+    return lj;
 }
 
 // Run `steps` steps for chains [0, C): per-chain state in/out, per-chain

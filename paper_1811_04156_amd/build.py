@@ -16,8 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librjpath.so")
 SOURCES = ["rj_run_f32.hip", "rj_run_f64.hip", "rj_run_f32_mala.hip", "rj_run_f64_mala.hip", "rj_run_f32_lmala.hip",
-           "rj_run_f64_lmala.hip",
-           "rj_sampler.hip", "rj_anchor.hip", "rj_stats.hip", "rj_noalloc.hip", "rj_api.hip"]
+           "rj_run_f64_lmala.hip", "rj_run_f32_tree.hip", "rj_run_f64_tree.hip",
+           "rj_sampler.hip", "rj_anchor.hip", "rj_stats.hip", "rj_noalloc.hip", "rj_observe.hip", "rj_api.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -382,11 +382,12 @@ int check_run(const rjpath_medium* m, const rjpath_targets* t, const rjpath_chai
     if (p->n_perturb < p->cycle_len && (p->birth_thresh == 0u))
         return fail(RJPATH_EINVAL, "birth_thresh must be > 0 when jump steps are scheduled");
     if (!(p->sigma > 0) || !(p->kappa_end > 0)) return fail(RJPATH_EINVAL, "sigma and kappa_end must be > 0");
-    if (p->sampler != RJPATH_PLAIN && p->sampler != RJPATH_MALA && p->sampler != RJPATH_LMALA)
+    if (p->sampler != RJPATH_PLAIN && p->sampler != RJPATH_MALA && p->sampler != RJPATH_LMALA &&
+        p->sampler != RJPATH_TREE)
         return fail(RJPATH_EINVAL, "bad sampler");
     if (p->sampler != RJPATH_PLAIN && !(p->mala_h > 0)) return fail(RJPATH_EINVAL, "mala_h must be > 0");
-    if (p->sampler == RJPATH_MALA && !c->work)
-        return fail(RJPATH_EINVAL, "the joint Langevin sampler needs the chains' work buffer");
+    if ((p->sampler == RJPATH_MALA || p->sampler == RJPATH_TREE) && !c->work)
+        return fail(RJPATH_EINVAL, "the joint Langevin and tree samplers need the chains' work buffer");
     if (p->block_chains != 0 && (p->block_chains % 64 != 0 || p->block_chains < 64 || p->block_chains > 256))
         return fail(RJPATH_EINVAL, "block_chains must be 64, 128, 192 or 256");
     if (p->v_lds < 0 || p->v_lds > c->cap) return fail(RJPATH_EINVAL, "v_lds must lie in [0, cap]");
@@ -489,6 +490,115 @@ int rjpath_autotune(rjpath_medium* m, const rjpath_targets* t, const rjpath_chai
     return RJPATH_OK;
 }
 
+int rjpath_tune_proposal(rjpath_medium* m, const rjpath_targets* t, const rjpath_chains* c, const rjpath_run_params* p,
+                         int32_t n_cand, const rjpath_proposal* cand, int32_t trial_steps, int32_t groups,
+                         double* score, int32_t* best, void* stream) {
+    int r = check_run(m, t, c, p);
+    if (r) return r;
+    if (n_cand < 1 || !cand) return fail(RJPATH_EINVAL, "need at least one candidate");
+    if (trial_steps < 1) return fail(RJPATH_EINVAL, "trial_steps must be >= 1");
+    if (groups < 2 || groups > 64) return fail(RJPATH_EINVAL, "groups must lie in [2, 64]");
+    if (p->step_counter || p->trace) return fail(RJPATH_EINVAL, "rjpath_tune_proposal takes a host step0 and no trace");
+    for (int i = 0; i < n_cand; ++i) {
+        rjpath_run_params q = *p;
+        q.sigma = cand[i].sigma;
+        q.kappa_end = cand[i].kappa_end;
+        q.mala_h = cand[i].mala_h;
+        q.cycle_len = cand[i].cycle_len;
+        q.n_perturb = cand[i].n_perturb;
+        r = check_run(m, t, c, &q);
+        if (r) return fail(r, "candidate " + std::to_string(i) + ": " + g_err);
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const int T = t->n_targets;
+    // the trials' statistics go to a buffer of their own: the caller's are untouched
+    double* tstats = nullptr;
+    const size_t nst = (size_t)c->n_chains * RJPATH_NSTAT;
+    if (hipMalloc((void**)&tstats, sizeof(double) * nst) != hipSuccess)
+        return fail(RJPATH_ENOMEM, "trial statistics allocation");
+    rjpath_chains cc = *c;
+    cc.stats = tstats;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    std::vector<double> ms(n_cand, 0.0), r2sum(n_cand, 0.0);
+    std::vector<double> ones(T, 1.0), I(T), se(T);
+    uint64_t step = p->step0;
+    auto cleanup = [&]() {
+        if (e0) hipEventDestroy(e0);
+        if (e1) hipEventDestroy(e1);
+        hipFree(tstats);
+    };
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        cleanup();
+        return fail(RJPATH_EHIP, "hipEventCreate");
+    }
+    // two passes, the second in reverse order, so that slow drift of the
+    // chains during the trials favours no candidate
+    for (int pass = 0; pass < 2 && r == RJPATH_OK; ++pass)
+        for (int j = 0; j < n_cand && r == RJPATH_OK; ++j) {
+            const int i = pass == 0 ? j : n_cand - 1 - j;
+            rjpath_run_params q = *p;
+            q.sigma = cand[i].sigma;
+            q.kappa_end = cand[i].kappa_end;
+            q.mala_h = cand[i].mala_h;
+            q.cycle_len = cand[i].cycle_len;
+            q.n_perturb = cand[i].n_perturb;
+            q.step0 = step;
+            q.burn_in = (int64_t)step; // every trial step is sampled
+            q.steps = trial_steps;
+            q.hist = nullptr;
+            q.chunk = 0;
+            hipError_t e = fill_f64(tstats, nst, 0.0, s);
+            if (e == hipSuccess) e = hipEventRecord(e0, s);
+            if (e != hipSuccess) {
+                r = hip_fail(e, "trial setup");
+                break;
+            }
+            r = rjpath_run_chains(m, t, &cc, &q, stream);
+            if (r) break;
+            e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float t_ms = 0;
+            if (e == hipSuccess) e = hipEventElapsedTime(&t_ms, e0, e1);
+            if (e != hipSuccess) {
+                r = hip_fail(e, "trial timing");
+                break;
+            }
+            ms[i] += t_ms;
+            step += trial_steps;
+            // relative error of each target's estimator ratio over this trial
+            // (the anchor cancels in se / I)
+            int rr = rjpath_intensity(m, t, &cc, groups, ones.data(), I.data(), se.data(), nullptr, nullptr, stream);
+            if (rr != RJPATH_OK && rr != RJPATH_ENODATA) {
+                r = rr;
+                break;
+            }
+            std::vector<double> rel;
+            for (int k = 0; k < T; ++k)
+                if (I[k] > 0 && se[k] > 0) rel.push_back((se[k] / I[k]) * (se[k] / I[k]));
+            double med = INFINITY; // a trial without any usable target scores 0
+            if (!rel.empty()) {
+                std::nth_element(rel.begin(), rel.begin() + rel.size() / 2, rel.end());
+                med = rel[rel.size() / 2];
+            }
+            r2sum[i] += med;
+        }
+    cleanup();
+    if (r) return r;
+    int bi = 0;
+    double bs = -1;
+    for (int i = 0; i < n_cand; ++i) {
+        // ESS per second of the median target: 1 / (r^2 x time), both passes together
+        const double sc = r2sum[i] > 0 && std::isfinite(r2sum[i]) ? 4.0 / (r2sum[i] * ms[i] * 1e-3) : 0.0;
+        if (score) score[i] = sc;
+        if (sc > bs) {
+            bs = sc;
+            bi = i;
+        }
+    }
+    if (best) *best = bi;
+    return RJPATH_OK;
+}
+
 int rjpath_grad(rjpath_medium* m, const rjpath_targets* t, const rjpath_chains* c, double* logp_out, void* dlogp_dv,
                 double* score, void* stream) {
     int r = check_common(m, t, c);
@@ -563,6 +673,81 @@ int rjpath_intensity_noalloc(rjpath_medium* m, const rjpath_targets* t, const rj
     KArgs a = make_args(m, t, c);
     HIPCHK(launch_intensity_noalloc(a, groups, anchor, m->d_gl, I, se, ess, rhat, (hipStream_t)stream),
            "rjpath_intensity_noalloc kernels");
+    return RJPATH_OK;
+}
+
+int rjpath_yield_accumulate(rjpath_medium* m, const rjpath_targets* t, const rjpath_chains* c, int32_t n_pairs,
+                            const int32_t* pairs, const int32_t* role, int32_t groups, double* acc, double* logr,
+                            void* stream) {
+    int r = check_common(m, t, c);
+    if (r) return r;
+    if (n_pairs < 1) return fail(RJPATH_EINVAL, "n_pairs must be >= 1");
+    if (!pairs || !role || !acc) return fail(RJPATH_EINVAL, "null pairs, role or acc");
+    if (groups < 2 || groups > 64) return fail(RJPATH_EINVAL, "groups must lie in [2, 64]");
+    KArgs a = make_args(m, t, c);
+    HIPCHK(launch_yield(a, n_pairs, pairs, role, groups, acc, logr, (hipStream_t)stream), "yield kernel launch");
+    return RJPATH_OK;
+}
+
+int rjpath_yield(int32_t n_pairs, int32_t groups, const double* acc, double* B, double* se, void* stream) {
+    if (n_pairs < 1) return fail(RJPATH_EINVAL, "n_pairs must be >= 1");
+    if (groups < 2 || groups > 64) return fail(RJPATH_EINVAL, "groups must lie in [2, 64]");
+    if (!acc) return fail(RJPATH_EINVAL, "null acc");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t na = (size_t)n_pairs * 2 * groups * 2;
+    std::vector<double> h(na);
+    HIPCHK(hipMemcpyAsync(h.data(), acc, sizeof(double) * na, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+    HIPCHK(hipStreamSynchronize(s), "hipStreamSynchronize");
+    bool nodata = false;
+    for (int k = 0; k < n_pairs; ++k) {
+        // side-wise sums of sqrt(r) / w and 1 / w; the bridge is their ratio of ratios
+        auto at = [&](int side, int g, int j) { return h[(((size_t)k * 2 + side) * groups + g) * 2 + j]; };
+        double S[2] = {0, 0}, W[2] = {0, 0};
+        for (int side = 0; side < 2; ++side)
+            for (int g = 0; g < groups; ++g) {
+                S[side] += at(side, g, 0);
+                W[side] += at(side, g, 1);
+            }
+        double Bk = NAN, sek = NAN;
+        if (W[0] > 0 && W[1] > 0 && S[1] > 0) {
+            Bk = (S[0] / W[0]) / (S[1] / W[1]);
+            std::vector<double> jk;
+            for (int g = 0; g < groups; ++g) {
+                if (at(0, g, 1) == 0 && at(1, g, 1) == 0) continue;
+                const double w0 = W[0] - at(0, g, 1), w1 = W[1] - at(1, g, 1), s1 = S[1] - at(1, g, 0);
+                if (!(w0 > 0) || !(w1 > 0) || !(s1 > 0)) {
+                    jk.clear();
+                    break;
+                }
+                jk.push_back(((S[0] - at(0, g, 0)) / w0) / (s1 / w1));
+            }
+            const int G = (int)jk.size();
+            if (G >= 2) {
+                double mj = 0, ss = 0;
+                for (double v : jk) mj += v;
+                mj /= G;
+                for (double v : jk) ss += (v - mj) * (v - mj);
+                sek = std::sqrt((G - 1.0) / G * ss);
+            }
+        } else {
+            nodata = true;
+        }
+        if (B) B[k] = Bk;
+        if (se) se[k] = sek;
+    }
+    if (nodata) return fail(RJPATH_ENODATA, "a pair has no samples on one side (or no overlap)");
+    return RJPATH_OK;
+}
+
+int rjpath_length_hist(rjpath_medium* m, const rjpath_targets* t, const rjpath_chains* c, int32_t bins, double l0,
+                       double bin_width, double* hist, void* stream) {
+    int r = check_common(m, t, c);
+    if (r) return r;
+    if (bins < 1 || bins > (1 << 20)) return fail(RJPATH_EINVAL, "bins must lie in [1, 2^20]");
+    if (!(bin_width > 0) || !std::isfinite(l0)) return fail(RJPATH_EINVAL, "bin_width must be > 0 and l0 finite");
+    if (!hist) return fail(RJPATH_EINVAL, "null hist");
+    KArgs a = make_args(m, t, c);
+    HIPCHK(launch_lhist(a, bins, l0, bin_width, hist, (hipStream_t)stream), "length histogram kernel launch");
     return RJPATH_OK;
 }
 

@@ -121,10 +121,12 @@ hipError_t launch_run(const KArgs& a, int block, hipStream_t s) {
     if (a.prec == RJPATH_F64) {
         if (a.sampler == RJPATH_MALA) return launch_run_v<double, 1>(a, block, s);
         if (a.sampler == RJPATH_LMALA) return launch_run_v<double, 2>(a, block, s);
+        if (a.sampler == RJPATH_TREE) return launch_run_v<double, 3>(a, block, s);
         return launch_run_v<double, 0>(a, block, s);
     }
     if (a.sampler == RJPATH_MALA) return launch_run_v<float, 1>(a, block, s);
     if (a.sampler == RJPATH_LMALA) return launch_run_v<float, 2>(a, block, s);
+    if (a.sampler == RJPATH_TREE) return launch_run_v<float, 3>(a, block, s);
     return launch_run_v<float, 0>(a, block, s);
 }
 
@@ -132,9 +134,11 @@ hipError_t set_run_lds_limit() {
     hipError_t e = set_lds_limit_v<float, 0>();
     if (e == hipSuccess) e = set_lds_limit_v<float, 1>();
     if (e == hipSuccess) e = set_lds_limit_v<float, 2>();
+    if (e == hipSuccess) e = set_lds_limit_v<float, 3>();
     if (e == hipSuccess) e = set_lds_limit_v<double, 0>();
     if (e == hipSuccess) e = set_lds_limit_v<double, 1>();
     if (e == hipSuccess) e = set_lds_limit_v<double, 2>();
+    if (e == hipSuccess) e = set_lds_limit_v<double, 3>();
     return e;
 }
 __global__ void advance_kernel(uint64_t* counter, uint64_t steps) {

@@ -30,10 +30,10 @@
 
 namespace rj {
 
-enum { MV_INTERIOR = 0, MV_END = 1, MV_BIRTH = 2, MV_DEATH = 3, MV_MALA = 4, MV_NULL = 5, MV_LMALA = 6 };
+enum { MV_INTERIOR = 0, MV_END = 1, MV_BIRTH = 2, MV_DEATH = 3, MV_MALA = 4, MV_NULL = 5, MV_LMALA = 6, MV_TREE = 7 };
 
-// Interior-vertex move of the sampler (RJPATH_PLAIN / _MALA / _LMALA).
-enum { SAMP_PLAIN = 0, SAMP_JOINT = 1, SAMP_LOCAL = 2 };
+// Interior-vertex move of the sampler (RJPATH_PLAIN / _MALA / _LMALA / _TREE).
+enum { SAMP_PLAIN = 0, SAMP_JOINT = 1, SAMP_LOCAL = 2, SAMP_TREE = 3 };
 
 // Lane-private path storage: slots below V in LDS, the rest in HBM.  LO: the
 // whole path is known to be in LDS.  The LDS side is addressed through an
@@ -484,10 +484,168 @@ template <class R> __device__ __forceinline__ void fold_hist(Lane<R>& ln, const 
 
 
 // One step of one lane; returns the move kind, writes log A / accepted / index.
+// ---------------------------------------------------------------------------
+// Tree-coordinate move of the whole path (App. "Path space coordinate
+// system"; Sec. "Path proposal distribution").  Interval (k, l), l - k >= 2,
+// places vertex m = (k + l) / 2 by bi-spherical coordinates (zeta, t, phi)
+// about the foci f_k, f_l (cos s = tanh zeta), then splits into (k, m) and
+// (m, l); the root is (0, n - 1).  The azimuth is measured in a frame handed
+// down the tree: the root's is the orthonormal completion of its axis, a
+// child's has e3 = the unit normal of the plane of its parent's foci and
+// vertex (the parent's frame turned about the parent's axis to the parent
+// vertex's azimuth, then rotated onto the child's axis) and e2 = e3 x e1.
+// The move draws a von Mises-Fisher step of the end point on the sensor
+// (words 4, 5, as the end-point perturbation) and Gaussian steps of variance
+// mala_h / n for every (zeta, t, phi) (vertex m: one Philox block with
+// counter word 3 = 2 + m), builds the proposal top-down level by level (each
+// vertex's foci and frame come from vertices placed before it) into the work
+// buffer, and accepts with
+//   log A = log p(y) - log p(x) + sum_m [log J_m(y) - log J_m(x)],
+//   J_m = gamma^3 sech^2(zeta) / (cosh t - tanh zeta)^3.
+// The coordinates are formed from unit vectors: with uA, uB the unit vectors
+// from f_m to its foci, 1 + cos s = |uA + uB|^2 / 2, 1 - cos s = |uA - uB|^2 / 2
+// and sin s = |uA + uB| |uA - uB| / 2, which keep their precision for nearly
+// straight (s ~ pi) and nearly folded paths.
+// ---------------------------------------------------------------------------
+template <class R> struct TreePath {
+    // the proposal: vertex 0 from the path, interior vertices from the work
+    // buffer, the end point held apart
+    GlobalPath<R> work;
+    V3<R> y0, yend;
+    int n;
+    __device__ __forceinline__ V3<R> p(int v) const { return v == 0 ? y0 : (v == n - 1 ? yend : work.p(v)); }
+    __device__ __forceinline__ void stw(int, R) const {}
+};
+
+// frame of interval (k, l) of a path: root -> onb of the axis; otherwise from
+// the parent interval (kp, lp) and its vertex fp
+template <class R>
+__device__ __forceinline__ void tree_frame(bool root, V3<R> e1, V3<R> fkp, V3<R> flp, V3<R> fp, V3<R>& e2,
+                                           V3<R>& e3) {
+    if (root) {
+        onb(e1, e2, e3);
+        return;
+    }
+    const V3<R> ep = unit_dir(fkp, flp);
+    const V3<R> g = fp - fkp;
+    V3<R> c = {ep.y * g.z - ep.z * g.y, ep.z * g.x - ep.x * g.z, ep.x * g.y - ep.y * g.x};
+    e3 = Mth<R>::rsqrt(dot(c, c)) * c;
+    e2 = {e3.y * e1.z - e3.z * e1.y, e3.z * e1.x - e3.x * e1.z, e3.x * e1.y - e3.y * e1.x};
+}
+
+template <class R, bool LO>
+__device__ __forceinline__ void tree_move(const Tgt<R>& T, const PathRef<R, LO>& ps, const GlobalPath<R>& work,
+                                          Lane<R>& ln, const StepCtx& sc, uint64_t step, const uint32_t r[8],
+                                          R logu, int& accepted, R& logA) {
+    const int n = ln.n;
+    const V3<R> x0 = ps.p(0), xe = ps.p(n - 1);
+    // end point: von Mises-Fisher step about the current sensor normal
+    V3<R> yend;
+    {
+        const R u4 = unif<R>(r[4]), u5 = unif<R>(r[5]);
+        const R lg = Mth<R>::log(u4 + ((R)1 - u4) * (R)sc.e2k);
+        const V3<R> dd = from_eta(T, xe);
+        const V3<R> nu = Mth<R>::rsqrt(dot(dd, dd)) * dd;
+        V3<R> e2, e3;
+        onb(nu, e2, e3);
+        const R omw = -lg * (R)sc.ikappa;
+        const R sw = Mth<R>::sqrt(fmax(omw * ((R)2 - omw), (R)0));
+        const V3<R> nn = ((R)1 - omw) * nu + sw * (Mth<R>::cos2pi(u5) * e2 + Mth<R>::sin2pi(u5) * e3);
+        yend = T.eta + (T.eta_lo + T.rad * nn);
+    }
+    auto xat = [&](int v) __attribute__((always_inline)) { return ps.p(v); };
+    auto yat = [&](int v) __attribute__((always_inline)) { return v == 0 ? x0 : (v == n - 1 ? yend : work.p(v)); };
+    const R sig = Mth<R>::sqrt((R)sc.mala_h / (R)n);
+    double lj = 0.0; // sum of log J(y) - log J(x)
+    bool ok = true;
+    for (int d = 0;; ++d) {
+        bool any = false;
+        for (int j = 0; j < (1 << d); ++j) {
+            // interval of node (d, j) and of its parent, by descent from the root
+            int k = 0, l = n - 1, kp = 0, lp = n - 1;
+            for (int b = d - 1; b >= 0; --b) {
+                const int mid = (k + l) >> 1;
+                kp = k;
+                lp = l;
+                if ((j >> b) & 1)
+                    k = mid;
+                else
+                    l = mid;
+            }
+            if (l - k < 2) continue;
+            any = true;
+            const int m = (k + l) >> 1, pm = (kp + lp) >> 1;
+            const bool root = d == 0;
+            // current coordinates of x_m
+            const V3<R> xk = xat(k), xl = xat(l), xm = xat(m);
+            const V3<R> rx = xl - xk;
+            const R gx = (R)0.5 * Mth<R>::sqrt(dot(rx, rx));
+            const V3<R> e1x = ((R)0.5 * Mth<R>::rcp(gx)) * rx;
+            V3<R> e2x, e3x;
+            tree_frame(root, e1x, xat(kp), xat(lp), xat(pm), e2x, e3x);
+            const V3<R> va = xk - xm, vb = xl - xm;
+            const R dA = Mth<R>::sqrt(dot(va, va)), dB = Mth<R>::sqrt(dot(vb, vb));
+            const V3<R> ua = Mth<R>::rcp(dA) * va, ub = Mth<R>::rcp(dB) * vb;
+            const V3<R> sp = ua + ub, sm = ua - ub;
+            const R np2 = dot(sp, sp), nm2 = dot(sm, sm);
+            const R zeta = (R)0.5 * Mth<R>::log(np2 * Mth<R>::rcp(nm2));
+            const R tt = Mth<R>::log(dA * Mth<R>::rcp(dB));
+            const V3<R> q = xm - (R)0.5 * (xk + xl);
+            const R phi = atan2(dot(q, e3x), dot(q, e2x));
+            // log J(x): sech zeta = sin s, cosh t - tanh zeta = (dA - dB)^2 / (2 dA dB) + (1 - cos s)
+            const R dd = dA - dB;
+            const R denx = dd * dd * Mth<R>::rcp((R)2 * dA * dB) + (R)0.5 * nm2;
+            lj -= (double)((R)3 * Mth<R>::log(gx) + Mth<R>::log((R)0.25 * np2 * nm2) - (R)3 * Mth<R>::log(denx));
+            // proposed coordinates
+            uint32_t qd[4] = {sc.chain, (uint32_t)step, (uint32_t)(step >> 32), 2u + (uint32_t)m};
+            philox4x32_10(qd, sc.k0, sc.k1);
+            V3<R> xi;
+            box_muller3<R>(qd[0], qd[1], qd[2], qd[3], xi);
+            const R z2 = zeta + sig * xi.x, t2 = tt + sig * xi.y, p2 = phi + sig * xi.z;
+            // y_m from its (already placed) foci and frame
+            const V3<R> yk = yat(k), yl = yat(l);
+            const V3<R> ry = yl - yk;
+            const R gy = (R)0.5 * Mth<R>::sqrt(dot(ry, ry));
+            const V3<R> e1y = ((R)0.5 * Mth<R>::rcp(gy)) * ry;
+            V3<R> e2y, e3y;
+            tree_frame(root, e1y, yat(kp), yat(lp), yat(pm), e2y, e3y);
+            // tanh and sech of zeta and cosh t - tanh zeta without cancellation
+            const R az = fabs(z2);
+            const R ez = Mth<R>::exp((R)-2 * az);
+            const R th = copysign(((R)1 - ez) * Mth<R>::rcp((R)1 + ez), z2);
+            const R sh = (R)2 * Mth<R>::sqrt(ez) * Mth<R>::rcp((R)1 + ez);
+            const R et = Mth<R>::exp(t2), iet = Mth<R>::rcp(et);
+            const R sht = (R)0.5 * (et - iet);
+            const R s2h = sht * sht * Mth<R>::rcp((R)0.5 * (et + iet) + (R)1); // cosh t - 1 = sinh^2 t / (cosh t + 1)
+            const R omt = z2 > (R)0 ? (R)2 * ez * Mth<R>::rcp((R)1 + ez) : (R)1 - th; // 1 - tanh zeta
+            const R deny = s2h + omt;
+            const V3<R> dir = sht * e1y + sh * (Mth<R>::cos2pi(p2 * (R)0.15915494309189534) * e2y +
+                                                Mth<R>::sin2pi(p2 * (R)0.15915494309189534) * e3y);
+            const V3<R> ym = (R)0.5 * (yk + yl) + (gy * Mth<R>::rcp(deny)) * dir;
+            lj += (double)((R)3 * Mth<R>::log(gy) + (R)2 * Mth<R>::log(sh) - (R)3 * Mth<R>::log(deny));
+            ok = ok && isfinite(ym.x) && isfinite(ym.y) && isfinite(ym.z);
+            work.glb[(size_t)m * work.C] = Vtx<R>{ym.x, ym.y, ym.z, (R)0};
+        }
+        if (!any) break;
+    }
+    double L;
+    const double lpx = full_logp(T, ps, n, L);
+    const TreePath<R> yp{work, x0, yend, n};
+    const double lpy = ok ? full_logp(T, yp, n, L) : -__builtin_inf();
+    const double la = lpy - lpx + lj;
+    logA = isfinite(lpy) && isfinite(la) ? (R)la : Mth<R>::ninf();
+    if (logu < logA) {
+        accepted = 1;
+        for (int k = 1; k <= n - 2; ++k) ps.st(k, work.ld(k));
+        ps.st(n - 1, Vtx<R>{yend.x, yend.y, yend.z, (R)0});
+        full_logp(T, ps, n, ln.L); // refresh the cached depths and L
+    }
+}
+
 template <class R, bool LO, int SAMP>
 __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>& ps, const GlobalPath<R>& work,
-                                          Lane<R>& ln, const StepCtx& sc, uint64_t step, bool perturb, int& move,
-                                          int& idx, int& accepted, R& logA, R& logu) {
+                                          Lane<R>& ln, const StepCtx& sc, uint64_t step, bool perturb, bool tree,
+                                          int& move, int& idx, int& accepted, R& logA, R& logu) {
     uint32_t r[8];
     draw8(sc, step, r);
     const int n = ln.n;
@@ -498,6 +656,13 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
     accepted = 0;
     logA = Mth<R>::ninf();
     const V3<R> ex = {(R)1, (R)0, (R)0};
+    if constexpr (SAMP == SAMP_TREE) {
+        if (tree) {
+            move = MV_TREE;
+            tree_move<R, LO>(T, ps, work, ln, sc, step, r, logu, accepted, logA);
+            return;
+        }
+    }
     if (perturb) {
         const int j = 1 + pick(r[0], (uint32_t)(n - 1));
         idx = j;
@@ -819,13 +984,15 @@ __device__ __forceinline__ void one_step(const KArgs& a, const Tgt<R>& T, const 
     int move, idx, accepted;
     R logA, logu;
     const bool counted = (int64_t)step >= a.burn_in;
-    step_body<R, LO, SAMP>(T, ps, work, ln, sc, step, perturb, move, idx, accepted, logA, logu);
+    // the tree sampler makes the first step of every cycle a tree-coordinate move
+    const bool tree = SAMP == SAMP_TREE && phase == 0 && perturb;
+    step_body<R, LO, SAMP>(T, ps, work, ln, sc, step, perturb, tree, move, idx, accepted, logA, logu);
     {
         // move counts, branch-free (per-branch updates get merged by the
         // compiler into a dynamically indexed stack slot)
         const uint32_t cu = counted ? 1u : 0u, ca = (uint32_t)accepted;
         const uint32_t ib = cu & (move == MV_BIRTH ? 1u : 0u), id = cu & (move == MV_DEATH ? 1u : 0u);
-        const uint32_t ip = cu - ib - id, im = cu & ((move == MV_MALA || move == MV_LMALA) ? 1u : 0u);
+        const uint32_t ip = cu - ib - id, im = cu & ((move == MV_MALA || move == MV_LMALA || move == MV_TREE) ? 1u : 0u);
         ln.ne += cu & (((move == MV_BIRTH || move == MV_DEATH) && idx < 0) ? 1u : 0u);
         ln.pb += ib;
         ln.pd += id;

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "librjpath.so")
 
 RJPATH_OK, RJPATH_EINVAL, RJPATH_ENOMEM, RJPATH_EHIP, RJPATH_ENODATA, RJPATH_ENOTSUP = 0, -1, -2, -3, -4, -5
 F32, F64 = 0, 1
-PLAIN, MALA, LMALA = 0, 1, 2
+PLAIN, MALA, LMALA, TREE = 0, 1, 2, 3
 NSTAT = 16
 TRACE_WORDS = 5
 
@@ -48,9 +48,15 @@ class RunParams(C.Structure):
                 ("hist", _p), ("step_counter", _p)]
 
 
+class Proposal(C.Structure):
+    _fields_ = [("sigma", C.c_double), ("kappa_end", C.c_double), ("mala_h", C.c_double), ("cycle_len", C.c_int32),
+                ("n_perturb", C.c_int32)]
+
+
 EXPORTS = ["rjpath_last_error", "rjpath_version", "rjpath_init_medium", "rjpath_free_medium", "rjpath_run_chains",
            "rjpath_anchor", "rjpath_intensity", "rjpath_grad", "rjpath_autotune", "rjpath_tune_tilt", "rjpath_dlogi_dtheta",
-           "rjpath_intensity_noalloc"]
+           "rjpath_intensity_noalloc", "rjpath_yield_accumulate", "rjpath_yield", "rjpath_length_hist",
+           "rjpath_tune_proposal"]
 
 _lib = None
 
@@ -84,6 +90,13 @@ def load(path: str = LIB_PATH):
     L.rjpath_dlogi_dtheta.argtypes = [_p, C.POINTER(Targets), _p, _p, _p]
     L.rjpath_intensity_noalloc.argtypes = [_p, C.POINTER(Targets), C.POINTER(Chains), C.c_int32, _p, _p, _p, _p, _p,
                                            _p]
+    L.rjpath_yield_accumulate.argtypes = [_p, C.POINTER(Targets), C.POINTER(Chains), C.c_int32, _p, _p, C.c_int32,
+                                          _p, _p, _p]
+    L.rjpath_yield.argtypes = [C.c_int32, C.c_int32, _p, _p, _p, _p]
+    L.rjpath_length_hist.argtypes = [_p, C.POINTER(Targets), C.POINTER(Chains), C.c_int32, C.c_double, C.c_double,
+                                     _p, _p]
+    L.rjpath_tune_proposal.argtypes = [_p, C.POINTER(Targets), C.POINTER(Chains), C.POINTER(RunParams), C.c_int32,
+                                       C.POINTER(Proposal), C.c_int32, C.c_int32, _p, C.POINTER(C.c_int32), _p]
     for f in EXPORTS[2:]:
         getattr(L, f).restype = C.c_int
     _lib = L
@@ -212,7 +225,7 @@ class Sampler:
     def _params(self, steps, run=None, trace=None, hist=None, block=0, v_lds=0, chunk=0, step0=None, counter=None):
         r = dict(self.w)
         r.update(run or {})
-        if int(r.get("sampler", 0)) == MALA and self.work is None:
+        if int(r.get("sampler", 0)) in (MALA, TREE) and self.work is None:
             self.work = torch.zeros_like(self.verts)
         return RunParams(int(r["seed"]), int(self.step if step0 is None else step0), int(r["burn_in"]), int(steps),
                          int(r["cycle_len"]), int(r["n_perturb"]), birth_thresh(r["birth_frac"]), float(r["sigma"]),
@@ -313,6 +326,28 @@ class Sampler:
         self.step += steps
         return b.value, v.value
 
+    def tune_proposal(self, candidates, trial_steps, groups=16, run=None):
+        """rjpath_tune_proposal over candidate dicts with keys sigma,
+        kappa_end, mala_h, cycle_len, n_perturb (missing keys: the workload's
+        values).  Returns (best index, scores); the chains advance by
+        2 * len(candidates) * trial_steps steps."""
+        r = dict(self.w)
+        r.update(run or {})
+        arr = (Proposal * len(candidates))()
+        for i, c in enumerate(candidates):
+            arr[i] = Proposal(float(c.get("sigma", r["sigma"])), float(c.get("kappa_end", r["kappa_end"])),
+                              float(c.get("mala_h", r.get("mala_h", 0.05))), int(c.get("cycle_len", r["cycle_len"])),
+                              int(c.get("n_perturb", r["n_perturb"])))
+        p = self._params(trial_steps, run)
+        tg, ch = self._targets(), self._chains()
+        sc = np.zeros(len(candidates))
+        b = C.c_int32()
+        _check(load().rjpath_tune_proposal(self.medium.h, C.byref(tg), C.byref(ch), C.byref(p), len(candidates), arr,
+                                           int(trial_steps), int(groups), _np_ptr(sc), C.byref(b),
+                                           self._stream_ptr()))
+        self.step += 2 * len(candidates) * trial_steps
+        return b.value, sc
+
     def tune_tilt(self, rounds=4, steps=400, max_logw=40.0, floor_push=3.0, run=None):
         """Sector-tilt tuning in librjpath (rjpath_tune_tilt): `rounds` pilot
         rounds of `steps` steps, the tilt table updated on the device after
@@ -379,3 +414,46 @@ class Sampler:
         _check(load().rjpath_grad(self.medium.h, C.byref(tg), C.byref(ch), _tp(lp), _tp(g), _tp(sc),
                                   self._stream_ptr()))
         return lp, g, sc
+
+    # -- snapshot estimators --------------------------------------------------
+    def yield_pairs(self, pairs):
+        """Device tables of rjpath_yield_accumulate for a list of (t0, t1)
+        sensor pairs: (pairs (2P,), role (T,), P)."""
+        pr = np.asarray(pairs, np.int32).reshape(-1, 2)
+        role = np.full(self.T, -1, np.int32)
+        for k, (a, b) in enumerate(pr):
+            if role[a] >= 0 or role[b] >= 0 or a == b:
+                raise ValueError("each target may belong to one pair only")
+            role[a], role[b] = 2 * k, 2 * k + 1
+        return (torch.as_tensor(pr.reshape(-1), device=self.dev), torch.as_tensor(role, device=self.dev), len(pr))
+
+    def yield_accumulate(self, tables, acc=None, groups=16, logr=False):
+        """Adds one bridge sample per chain (rjpath_yield_accumulate); returns
+        (acc, per-chain log r or None)."""
+        pr, role, P = tables
+        if acc is None:
+            acc = torch.zeros((P, 2, groups, 2), dtype=torch.float64, device=self.dev)
+        lr = torch.empty(self.C, dtype=torch.float64, device=self.dev) if logr else None
+        tg, ch = self._targets(), self._chains()
+        _check(load().rjpath_yield_accumulate(self.medium.h, C.byref(tg), C.byref(ch), int(P), _tp(pr), _tp(role),
+                                              int(groups), _tp(acc), _tp(lr), self._stream_ptr()))
+        return acc, lr
+
+    def light_yield(self, acc):
+        """B = I_1 / I_0 and its standard error per pair (rjpath_yield)."""
+        P, _, groups, _ = acc.shape
+        B, se = np.zeros(P), np.zeros(P)
+        code = load().rjpath_yield(int(P), int(groups), _tp(acc), _np_ptr(B), _np_ptr(se), self._stream_ptr())
+        _check(code, allow=(RJPATH_ENODATA,))
+        return B, se
+
+    def length_hist(self, bins, l0, width, hist=None):
+        """Adds the current paths' lengths into per-target histograms
+        (rjpath_length_hist); returns the (T, bins + 1) tensor, whose last
+        column is the normaliser."""
+        if hist is None:
+            hist = torch.zeros((self.T, bins + 1), dtype=torch.float64, device=self.dev)
+        tg, ch = self._targets(), self._chains()
+        _check(load().rjpath_length_hist(self.medium.h, C.byref(tg), C.byref(ch), int(bins), float(l0), float(width),
+                                         _tp(hist), self._stream_ptr()))
+        return hist

@@ -1,0 +1,122 @@
+"""The calibration-shaped batch (strings of sensors in the 100-layer medium,
+flasher sources at sensor positions; the bulk calibration that motivates path
+integrals in the Introduction): device intensities and d log I / d theta
+against the FP64 oracle's estimators on the nearest targets of one flasher,
+and the gradient fit of the per-layer lengths lowering its loss."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1811_04156_amd import workloads as W
+from test_gpu_observe import _replicate
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+SOURCE = 35  # string 0, sensor 35 (z = 593.5 m): neighbours at 17 m and 34 m on the string
+
+
+@pytest.fixture(scope="module")
+def rj():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1811_04156_amd import rjpath
+    rjpath.load()
+    return rjpath
+
+
+def _oracle_estimates(w, chunks, chunk_steps, burn):
+    """The oracle's FP64 intensity (anchored estimator) and
+    d log I / d (lambda_s, lambda_a) per layer = E_p[d log p / d theta] from the
+    chains' paths after every chunk; the gradient's standard error from the
+    spread of the per-chain means."""
+    from oracle import oracle as O
+    orc = O.Oracle(w)
+    st = O.initial_state(w)
+    C = len(st["target"])
+    ids = np.arange(C) + 3_000_000
+    orc.run(w, st, burn, step0=0, chain_ids=ids)
+    stats = np.zeros((C, O.NSTAT))
+    L = int(w["m_layer_cnt"][0])
+    g = np.zeros((C, L, 2))
+    for k in range(chunks):
+        s, _ = orc.run(w, st, chunk_steps, step0=burn + k * chunk_steps, chain_ids=ids)
+        stats += s
+        for c in range(C):
+            _, ds, da, _ = orc.grad(int(st["target"][c]), st["verts"][c, : st["n"][c]])
+            g[c, :, 0] += ds
+            g[c, :, 1] += da
+    g /= chunks
+    anc = np.array([orc.anchor_I2(t) for t in range(len(w["t_src"]))])
+    I, se = O.intensity(w, stats, anc)
+    T = len(w["t_src"])
+    dm = np.zeros((T, L, 2))
+    dse = np.zeros((T, L, 2))
+    for t in range(T):
+        m = st["target"] == t
+        dm[t] = g[m].mean(0)
+        dse[t] = g[m].std(0, ddof=1) / math.sqrt(m.sum())
+    return I, se, dm, dse
+
+
+def test_near_targets_intensity_and_gradient_vs_oracle(rj):
+    """Four nearest targets of one flasher (17 m and 34 m along its string,
+    crossing 2-4 layers of 10 m): FP32 device intensity within 1% and 3
+    combined standard errors of the oracle's, and d log I / d lambda per layer
+    within 3 combined standard errors + 2% wherever the oracle's estimate is
+    significant (4 copies of each target on the device give its spread)."""
+    base = W.config5(sources=[SOURCE], chains_per_target=1, max_targets=4, cap=128)
+    copies = 4
+    w = _replicate(base, copies, 8192)
+    w["burn_in"] = 0
+    s = rj.Sampler(w, precision="f32")
+    s.run(2000)
+    s.stats.zero_()
+    score = torch.zeros((s.T, 1 + 3 * s.medium.L_total), dtype=torch.float64, device=s.dev)
+    for _ in range(20):
+        s.run(200)
+        s.grad(logp=False, score=score)
+    res = s.intensity(groups=16)
+    d = s.dlogI(score).cpu().numpy()[:, :, :2].reshape(copies, 4, -1, 2)
+    I = res["I"].reshape(copies, 4)
+    Id, Ise = I.mean(0), I.std(0, ddof=1) / math.sqrt(copies)
+    dd, ddse = d.mean(0), d.std(0, ddof=1) / math.sqrt(copies)
+    wo = dict(base)
+    wo["c_target"] = np.repeat(np.arange(4, dtype=np.int32), 1024)
+    wo["burn_in"] = 0
+    Io, seo, do, dose = _oracle_estimates(wo, chunks=60, chunk_steps=300, burn=2000)
+    worst = 0.0
+    for t in range(4):
+        rel = Id[t] / Io[t] - 1
+        sig = math.hypot(Ise[t], seo[t])
+        sig_d = np.hypot(ddse[t], dose[t])
+        sel = np.abs(do[t]) > 4 * dose[t]
+        err = np.abs(dd[t] - do[t])
+        if sel.any():
+            worst = max(worst, float(np.max(err[sel] / np.abs(do[t][sel]))))
+        print(f"target {t} ({np.linalg.norm(base['t_sensor'][t] - base['t_src'][t]):.0f} m): I device "
+              f"{Id[t]:.5e} +- {Ise[t] / Id[t]:.2%}, oracle {Io[t]:.5e} +- {seo[t] / Io[t]:.2%}, diff {rel:+.3%}; "
+              f"{sel.sum()} significant gradient entries, max |z| "
+              f"{np.max(err[sel] / sig_d[sel]) if sel.any() else 0:.2f}")
+        assert abs(Id[t] - Io[t]) < 3 * sig and abs(rel) < 0.01
+        assert sel.sum() >= 2
+        assert np.all(err[sel] < 3 * sig_d[sel] + 0.02 * np.abs(do[t][sel]))
+    print(f"worst relative gradient error among significant entries: {worst:.2%}")
+
+
+def test_fit_lowers_the_loss(rj):
+    """Gradient fit (Adam on log lambda) from the seeded perturbed start on a
+    two-flasher cut of the batch: the chi-square loss in log I drops below 40%
+    of its start and the rms log-intensity residual by at least a third."""
+    from paper_1811_04156_amd import calibration as K
+    w = W.config5(sources=[SOURCE, 400], chains_per_target=2048)
+    rep = K.fit(w, iters=12, lr=0.05)
+    h = rep["history"]
+    for r in h:
+        print(f"iter {r['iter']}: loss {r['loss']:.1f}, rms log I residual {r['rms_log_intensity_residual']:.4f}, "
+              f"rms log lambda error {r['rms_log_param_error']:.4f}")
+    last = min(r["loss"] for r in h[-3:])
+    assert last < 0.4 * h[0]["loss"]
+    assert min(r["rms_log_intensity_residual"] for r in h[-3:]) < (2 / 3) * h[0]["rms_log_intensity_residual"]

@@ -269,3 +269,62 @@ def test_autograd_on_device_theta(rj):
     I.sum().backward()
     assert theta.grad.device == theta.device and theta.grad.dtype == theta.dtype
     assert theta.grad[0, 1].item() > 0
+
+
+def test_proposal_tuner_runs_ordinary_steps_and_ranks(rj):
+    """rjpath_tune_proposal: every trial is ordinary sampler steps with the
+    candidate's parameters (a replay of the same sequence of runs ends in the
+    same state), the caller's statistics are untouched, and a candidate whose
+    interior step is 20x too small scores below the default proposal."""
+    w = W.layered_pairs(pairs=64, chains=1 << 16, cap=64, n_layers=12, dz=6.0, dmin=5.0, dmax=20.0)
+    w["burn_in"] = 0
+    a = rj.Sampler(w, precision="f32")
+    b = rj.Sampler(w, precision="f32")
+    a.run(500)
+    b.run(500)
+    before = a.stats.clone()
+    cands = [dict(), dict(sigma=0.05), dict(kappa_end=5.0, cycle_len=4, n_perturb=2)]
+    trial = 300
+    best, sc = a.tune_proposal(cands, trial)
+    order = [0, 1, 2, 2, 1, 0]
+    for i in order:
+        run = dict(cands[i])
+        b.run(trial, run=run)
+    torch.cuda.synchronize()
+    print("scores", sc, "best", best)
+    assert torch.equal(a.stats, before)
+    assert a.step == b.step
+    assert torch.equal(a.n, b.n)
+    used = (torch.arange(a.cap, device=a.n.device)[:, None] < a.n[None, :])[..., None]
+    assert torch.equal(a.verts[..., :3] * used, b.verts[..., :3] * used)
+    assert 0 <= best < len(cands) and np.all(sc > 0)
+    assert sc[1] < sc[0]
+
+
+def test_fp32_tree_sampler_intensity_matches_oracle(rj):
+    """The FP32 tree-coordinate sampler (a whole-path move on the first step
+    of every cycle) estimates the same intensity as the oracle's FP64 plain
+    sampler: within 3 combined standard errors and 1%."""
+    from oracle import oracle as O
+    w = W.single_target(6.0, 0.165, 3.0, 60.0, 0.9, chains=1 << 16, cap=64, burn_in=0, seed=41, sampler=3,
+                        mala_h=0.3)
+    s = rj.Sampler(w, precision="f32")
+    s.run(2000)
+    s.stats.zero_()
+    s.run(20000)
+    res = s.intensity(groups=16)
+    st = s.stats.cpu().numpy()
+    tree_acc = st[:, 14].sum() / st[:, 13].sum()
+    wo = dict(w)
+    wo["c_target"] = np.zeros(512, np.int32)
+    wo.update(burn_in=2000, sampler=0)
+    orc = O.Oracle(wo)
+    ost = O.initial_state(wo)
+    ostats, _ = orc.run(wo, ost, 40000, chain_ids=np.arange(512) + 5_000_000)
+    Io, seo = O.intensity(wo, ostats, np.array([orc.anchor_I2(0)]))
+    d = res["I"][0] - Io[0]
+    sig = math.hypot(res["se"][0], seo[0])
+    print(f"tree sampler: I {res['I'][0]:.5e} +- {res['se'][0] / res['I'][0]:.2%} (tree acceptance {tree_acc:.3f}); "
+          f"oracle plain {Io[0]:.5e} +- {seo[0] / Io[0]:.2%}; diff {d / Io[0]:+.3%} = {d / sig:+.2f} sigma")
+    assert st[:, 13].sum() >= (1 << 16) * 20000 // 5
+    assert abs(d) < 3 * sig and abs(d) < 0.01 * Io[0]

@@ -201,6 +201,44 @@ def test_fp64_local_langevin_free_run_matches_oracle(rj, which):
     assert np.array_equal(gst[:, 13:15], ostats[:, 13:15])
 
 
+@pytest.mark.parametrize("which", ["homog", "layered"])
+def test_fp64_tree_free_run_matches_oracle(rj, which):
+    """Tree-coordinate moves of the whole path (FP64): the device's level-by-
+    level construction of the proposal, its frames and the Jacobian terms give
+    the oracle's decisions and paths step by step, with longer paths (more
+    tree levels) in the layered case."""
+    if which == "homog":
+        w = W.single_target(6.0, 0.165, 3.0, 60.0, 0.9, chains=64, cap=32, burn_in=0, seed=31, sampler=3,
+                            mala_h=0.3, emit_kind=W.EMIT_VMF, emit_param=2.0, det_kind=W.DET_PAPER)
+    else:
+        w = mixed_workload(cap=32, chains=64)
+        w.update(burn_in=0, seed=37, sampler=3, mala_h=0.3)
+    steps = 800
+    s = rj.Sampler(w, precision="f64")
+    tr, _ = s.run(steps, trace=True)
+    torch.cuda.synchronize()
+    O, orc = _oracle(w)
+    st = O.initial_state(w)
+    ostats, otr = orc.run(w, st, steps, trace=True)
+    gtr = tr.cpu().numpy()
+    assert np.array_equal(gtr[..., 0], otr[..., 0])
+    tree = otr[..., 0] == 7
+    assert tree.sum() >= 64 * steps // 5
+    fin = np.isfinite(otr[..., 3])
+    assert np.array_equal(np.isfinite(gtr[..., 3]), fin)
+    assert np.allclose(gtr[..., 3][fin], otr[..., 3][fin], atol=1e-7, rtol=1e-8)
+    assert np.array_equal(gtr[..., 1], otr[..., 1])
+    acc = otr[..., 1][tree].mean()
+    print(f"{which}: {tree.sum()} tree moves, acceptance {acc:.3f}, n_max {st['n'].max()}")
+    assert acc > 0.02
+    n, V = s.get_state()
+    assert np.array_equal(n, st["n"])
+    for c in range(64):
+        assert np.allclose(V[c, : n[c]], st["verts"][c, : n[c]], atol=1e-8)
+    gst = s.stats.cpu().numpy()
+    assert np.array_equal(gst[:, 13:15], ostats[:, 13:15])
+
+
 def _lockstep_workload(which):
     if which == "homog":
         w = W.single_target(12.0, 0.165, 20.0, 80.0, 0.9, chains=64, cap=32, burn_in=0, seed=9)

@@ -333,10 +333,11 @@ def _group_se(per_group):
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("sampler,h", [(1, 0.01), (2, 0.3)])
+@pytest.mark.parametrize("sampler,h", [(1, 0.01), (2, 0.3), (3, 0.3)])
 def test_langevin_sector_occupancy_matches_tracer(oracle_mod, sampler, h):
     """With every interior perturbation a Langevin move (joint, or single
-    vertex), the chain on paths with n <= 4 spends time in sectors 3 and 4
+    vertex), or with the tree-coordinate move of the whole path on the first
+    step of every cycle, the chain on paths with n <= 4 spends time in sectors 3 and 4
     relative to sector 2 as I_3 / I_2 and I_4 / I_2, and its mean path length
     in sector 3 is the tracer's, whose photons detected after exactly one and
     two scatterings measure the same quantities."""
