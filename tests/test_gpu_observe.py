@@ -34,13 +34,8 @@ def _replicate(w, k, chains):
     """k independent copies of each target (copy j of target t is target
     j * T + t), `chains` chains each: independent estimates whose spread
     gives a standard error."""
-    w = dict(w)
-    T = len(w["t_src"])
-    for key in list(w):
-        if key.startswith("t_") and isinstance(w[key], np.ndarray) and len(w[key]) == T:
-            w[key] = np.concatenate([w[key]] * k)
-    w["c_target"] = np.repeat(np.arange(k * T, dtype=np.int32), chains)
-    return w
+    from paper_1811_04156_amd.table1 import replicate
+    return replicate(w, k, chains)
 
 
 def _golden():
@@ -143,9 +138,11 @@ def test_length_hist_counts_every_path(rj, chains):
         assert h[t, 40] == pytest.approx(wt[m].sum(), rel=1e-12)
 
 
-def _scenario_run(rj, b1, copies=8, chains=4096, burn=3000, snaps=40, every=250):
+def _scenario_run(rj, b1, copies=8, chains=4096, burn=20000, snaps=40, every=250):
+    # the tree-coordinate sampler: the local moves alone take ~10^6 steps to
+    # equilibrate the path length at a few optical depths
     w = _replicate(W.two_region(b1=b1, scale=SCALE, chains_per_sensor=1, cap=128), copies, chains)
-    w["burn_in"] = 0
+    w.update(burn_in=0, sampler=rj.TREE, mala_h=0.3)
     s = rj.Sampler(w, precision="f32")
     s.tune_tilt(rounds=3, steps=300)
     s.run(burn)
@@ -196,7 +193,9 @@ def test_two_region_length_distribution_vs_tracer(rj):
     """Path-length distribution of the detected light at both sensors
     (1 m bins): device histogram (8 independent copies) against the tracer's
     detected weight per bin normalised by its intensity; bins with at least
-    1% of the light are compared bin by bin (|z| < 4.5, mean z^2 < 2.5)."""
+    0.1% of the light (the forward-peaked light arrives within a few metres of
+    the straight distance, the tail is what scattering adds) are compared bin
+    by bin (|z| < 4.5, mean z^2 < 2.5)."""
     gold = _golden()
     b1 = 0.3
     _, _, _, _, h = _scenario_run(rj, b1)
@@ -207,7 +206,7 @@ def test_two_region_length_distribution_vs_tracer(rj):
         g = gold[(b1, k)]
         q = g["lh"][:47, 0] / g["I"]
         qse = np.sqrt((g["lh"][:47, 1] / g["I"]) ** 2 + (q * g["se"] / g["I"]) ** 2)
-        sel = q > 0.01
+        sel = q > 0.001
         z = (pm[sel] - q[sel]) / np.hypot(pse[sel], qse[sel])
         print(f"sensor {k}: {sel.sum()} bins, max |z| {np.abs(z).max():.2f}, mean z^2 {np.mean(z * z):.2f}; "
               f"mean length device {np.sum(pm * (np.arange(47) + 0.5)):.3f} m")
