@@ -102,8 +102,13 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-extras", action="store_true", help="skip the homogeneous batch and grad-vs-plain legs")
-    ap.add_argument("--sampler", choices=("plain", "langevin"), default="plain",
-                    help="interior move of the headline leg (plain Gaussian step or single-vertex Langevin)")
+    ap.add_argument("--sampler", choices=("plain", "langevin", "tree"), default="plain",
+                    help="interior move of the headline leg (plain Gaussian step, single-vertex Langevin, or "
+                         "tree-coordinate whole-path move on the first step of every cycle)")
+    ap.add_argument("--tree-h", type=float, default=0.3, help="variance scale of the tree-coordinate move")
+    ap.add_argument("--n-perturb", type=int, default=None,
+                    help="fixed number of perturbation steps per cycle of 5 for the headline leg (0: jumps only, "
+                         "5: perturbations only; skips the proposal tuner)")
     ap.add_argument("--lmala-h", type=float, default=0.05,
                     help="step-size scale of the single-vertex Langevin sampler in the grad-vs-plain leg")
     ap.add_argument("--proposal-trial", type=int, default=500,
@@ -186,7 +191,7 @@ def median_r(I, se):
 def proposal_candidates(w, sampler):
     """Proposal parameters the tuner tries (the workload's own first): the
     interior step, the mix of perturbation and jump steps, the end-point
-    concentration and, for the Langevin move, its step-size scale."""
+    concentration and, for the Langevin and tree moves, their step-size scale."""
     base = {k: w[k] for k in ("sigma", "kappa_end", "cycle_len", "n_perturb", "mala_h")}
     out = [dict(base)]
     for sig in (0.5, 1.0, 2.0, 4.0):
@@ -197,6 +202,9 @@ def proposal_candidates(w, sampler):
     if sampler == "langevin":
         for h in (0.02, 0.1, 0.2):
             out.append(dict(base, mala_h=h))
+    if sampler == "tree":
+        for h in (0.1, 1.0):
+            out.append(dict(base, mala_h=h))
     return out
 
 
@@ -204,9 +212,10 @@ def layered_headline(args):
     import torch
     from paper_1811_04156_amd import workloads as W
     from paper_1811_04156_amd.rjpath import Sampler
-    from paper_1811_04156_amd.rjpath import LMALA, PLAIN
+    from paper_1811_04156_amd.rjpath import LMALA, PLAIN, TREE
     w = W.config3()
-    w.update(burn_in=0, sampler=LMALA if args.sampler == "langevin" else PLAIN, mala_h=args.lmala_h)
+    samp = {"plain": PLAIN, "langevin": LMALA, "tree": TREE}[args.sampler]
+    w.update(burn_in=0, sampler=samp, mala_h=args.tree_h if args.sampler == "tree" else args.lmala_h)
     s = Sampler(w, device="cuda:0", precision="f32")
     C = s.C
     torch.cuda.synchronize()
@@ -214,9 +223,14 @@ def layered_headline(args):
     # untimed set-up: sector tilt (pilot rounds), launch autotuner (ordinary steps)
     s.tune_tilt(rounds=3, steps=args.chunk)
     block, vlds = s.autotune(2400)
-    cands = proposal_candidates(w, args.sampler)
-    best, scores = s.tune_proposal(cands, args.proposal_trial)
-    s.w.update(cands[best])
+    if args.n_perturb is None:
+        cands = proposal_candidates(w, args.sampler)
+        best, scores = s.tune_proposal(cands, args.proposal_trial)
+        s.w.update(cands[best])
+    else:
+        # a fixed move mix (profiling one move class): no proposal tuning
+        cands, best, scores = [dict()], 0, np.ones(1)
+        s.w.update(cycle_len=5, n_perturb=args.n_perturb)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t_setup
     s.anchor()  # computed once, before capture
