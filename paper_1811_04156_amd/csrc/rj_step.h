@@ -513,24 +513,37 @@ template <class R> struct TreePath {
     GlobalPath<R> work;
     V3<R> y0, yend;
     int n;
-    __device__ __forceinline__ V3<R> p(int v) const { return v == 0 ? y0 : (v == n - 1 ? yend : work.p(v)); }
+    __device__ __forceinline__ V3<R> p(int v) const {
+        // (selected per component: a choice between whole vectors would go
+        // through the stack)
+        const V3<R> g = work.p(v);
+        const bool s0 = v == 0, se = v == n - 1;
+        return {s0 ? y0.x : (se ? yend.x : g.x), s0 ? y0.y : (se ? yend.y : g.y), s0 ? y0.z : (se ? yend.z : g.z)};
+    }
     __device__ __forceinline__ void stw(int, R) const {}
 };
 
-// frame of interval (k, l) of a path: root -> onb of the axis; otherwise from
-// the parent interval (kp, lp) and its vertex fp
+// frame (e2, e3) of interval (k, l) of a path: root -> onb of the axis;
+// otherwise from the parent interval (kp, lp) and its vertex fp.  Both are
+// formed and one is selected by value (a choice between output references
+// would become a dynamically indexed stack slot).
+template <class R> struct Frame2 {
+    V3<R> e2, e3;
+};
+
 template <class R>
-__device__ __forceinline__ void tree_frame(bool root, V3<R> e1, V3<R> fkp, V3<R> flp, V3<R> fp, V3<R>& e2,
-                                           V3<R>& e3) {
-    if (root) {
-        onb(e1, e2, e3);
-        return;
-    }
+__device__ __forceinline__ Frame2<R> tree_frame(bool root, V3<R> e1, V3<R> fkp, V3<R> flp, V3<R> fp) {
+    V3<R> r2, r3;
+    onb(e1, r2, r3);
     const V3<R> ep = unit_dir(fkp, flp);
     const V3<R> g = fp - fkp;
-    V3<R> c = {ep.y * g.z - ep.z * g.y, ep.z * g.x - ep.x * g.z, ep.x * g.y - ep.y * g.x};
-    e3 = Mth<R>::rsqrt(dot(c, c)) * c;
-    e2 = {e3.y * e1.z - e3.z * e1.y, e3.z * e1.x - e3.x * e1.z, e3.x * e1.y - e3.y * e1.x};
+    const V3<R> c = {ep.y * g.z - ep.z * g.y, ep.z * g.x - ep.x * g.z, ep.x * g.y - ep.y * g.x};
+    const V3<R> c3 = Mth<R>::rsqrt(dot(c, c)) * c;
+    const V3<R> c2 = {c3.y * e1.z - c3.z * e1.y, c3.z * e1.x - c3.x * e1.z, c3.x * e1.y - c3.y * e1.x};
+    Frame2<R> f;
+    f.e2 = {root ? r2.x : c2.x, root ? r2.y : c2.y, root ? r2.z : c2.z};
+    f.e3 = {root ? r3.x : c3.x, root ? r3.y : c3.y, root ? r3.z : c3.z};
+    return f;
 }
 
 template <class R, bool LO>
@@ -554,7 +567,8 @@ __device__ __forceinline__ void tree_move(const Tgt<R>& T, const PathRef<R, LO>&
         yend = T.eta + (T.eta_lo + T.rad * nn);
     }
     auto xat = [&](int v) __attribute__((always_inline)) { return ps.p(v); };
-    auto yat = [&](int v) __attribute__((always_inline)) { return v == 0 ? x0 : (v == n - 1 ? yend : work.p(v)); };
+    const TreePath<R> yp{work, x0, yend, n};
+    auto yat = [&](int v) __attribute__((always_inline)) { return yp.p(v); };
     const R sig = Mth<R>::sqrt((R)sc.mala_h / (R)n);
     double lj = 0.0; // sum of log J(y) - log J(x)
     bool ok = true;
@@ -581,8 +595,8 @@ __device__ __forceinline__ void tree_move(const Tgt<R>& T, const PathRef<R, LO>&
             const V3<R> rx = xl - xk;
             const R gx = (R)0.5 * Mth<R>::sqrt(dot(rx, rx));
             const V3<R> e1x = ((R)0.5 * Mth<R>::rcp(gx)) * rx;
-            V3<R> e2x, e3x;
-            tree_frame(root, e1x, xat(kp), xat(lp), xat(pm), e2x, e3x);
+            const Frame2<R> fx = tree_frame(root, e1x, xat(kp), xat(lp), xat(pm));
+            const V3<R> e2x = fx.e2, e3x = fx.e3;
             const V3<R> va = xk - xm, vb = xl - xm;
             const R dA = Mth<R>::sqrt(dot(va, va)), dB = Mth<R>::sqrt(dot(vb, vb));
             const V3<R> ua = Mth<R>::rcp(dA) * va, ub = Mth<R>::rcp(dB) * vb;
@@ -607,8 +621,8 @@ __device__ __forceinline__ void tree_move(const Tgt<R>& T, const PathRef<R, LO>&
             const V3<R> ry = yl - yk;
             const R gy = (R)0.5 * Mth<R>::sqrt(dot(ry, ry));
             const V3<R> e1y = ((R)0.5 * Mth<R>::rcp(gy)) * ry;
-            V3<R> e2y, e3y;
-            tree_frame(root, e1y, yat(kp), yat(lp), yat(pm), e2y, e3y);
+            const Frame2<R> fy = tree_frame(root, e1y, yat(kp), yat(lp), yat(pm));
+            const V3<R> e2y = fy.e2, e3y = fy.e3;
             // tanh and sech of zeta and cosh t - tanh zeta without cancellation
             const R az = fabs(z2);
             const R ez = Mth<R>::exp((R)-2 * az);
@@ -630,7 +644,6 @@ __device__ __forceinline__ void tree_move(const Tgt<R>& T, const PathRef<R, LO>&
     }
     double L;
     const double lpx = full_logp(T, ps, n, L);
-    const TreePath<R> yp{work, x0, yend, n};
     const double lpy = ok ? full_logp(T, yp, n, L) : -__builtin_inf();
     const double la = lpy - lpx + lj;
     logA = isfinite(lpy) && isfinite(la) ? (R)la : Mth<R>::ninf();
