@@ -129,6 +129,11 @@ def parse():
     return ap.parse_args()
 
 
+def progress(msg):
+    """One line per finished leg on stderr (stdout carries only the JSON line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as fh:
@@ -213,7 +218,7 @@ def layered_headline(args):
     from paper_1811_04156_amd import workloads as W
     from paper_1811_04156_amd.rjpath import Sampler
     from paper_1811_04156_amd.rjpath import LMALA, PLAIN, TREE
-    w = W.config3()
+    w = W.layered_batch()
     samp = {"plain": PLAIN, "langevin": LMALA, "tree": TREE}[args.sampler]
     w.update(burn_in=0, sampler=samp, mala_h=args.tree_h if args.sampler == "tree" else args.lmala_h)
     s = Sampler(w, device="cuda:0", precision="f32")
@@ -357,13 +362,14 @@ def grad_vs_plain(h, max_steps, tree_h=0.3):
     from paper_1811_04156_amd.rjpath import LMALA, PLAIN, TREE, Sampler
     out = {}
     for name, samp, hh in (("plain", PLAIN, h), ("langevin", LMALA, h), ("tree", TREE, tree_h)):
-        w = W.config4()
+        w = W.layered_batch_langevin()
         w.update(burn_in=0, sampler=0)
         s = Sampler(w, device="cuda:0", precision="f32")
         s.tune_tilt(rounds=3, steps=300)
         run = dict(sampler=samp, mala_h=hh, burn_in=0)
         s.run(3000, run=run)
         steps, sec, r = _until_1pct(s, run, 4000, max_steps)
+        progress(f"grad-vs-plain: {name} sampler, {steps} steps, {sec:.1f} s, r = {r:.4f}")
         st = s.stats.cpu().numpy()
         out[name] = {"steps": steps, "seconds": sec, "median_rel_err": r, "reached_1pct": r <= 0.01,
                      "ess_per_s": 1.0 / (r * r * sec), "evals_per_s": evaluated(st) / sec,
@@ -382,7 +388,7 @@ def homogeneous_batch(chunk=1000, max_steps=40_000):
     import torch
     from paper_1811_04156_amd import workloads as W
     from paper_1811_04156_amd.rjpath import Sampler
-    w = W.config2()
+    w = W.homogeneous_groups()
     w["burn_in"] = 0
     s = Sampler(w, device="cuda:0", precision="f32")
     s.tune_tilt(rounds=3, steps=chunk)
@@ -416,7 +422,7 @@ def occupancy_probe(steps=1000):
     from paper_1811_04156_amd.rjpath import Sampler
     out = {}
     for pg in (256, 512):
-        w = W.config2(per_group=pg, cap=12)
+        w = W.homogeneous_groups(per_group=pg, cap=12)
         w["burn_in"] = 0
         s = Sampler(w, device="cuda:0", precision="f32")
         s.run(2000, block=64, v_lds=12)
@@ -436,7 +442,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (each GPU would run its own share "
-              "of the chains; see DESIGN.md)", file=sys.stderr)
+              "of the chains and the per-target sums would be all-reduced)", file=sys.stderr)
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -451,6 +457,7 @@ def main():
         print(json.dumps({"homogeneous_batch": homogeneous_batch(max_steps=args.hom_max_steps)}), flush=True)
         return
     head, w = layered_headline(args)
+    progress(f"headline leg done: {head['value']:.4g} evals/s, {head['ess_per_s']:.4g} ESS/s")
     out = {
         "metric": "path-density evals/s + ESS/s of detected intensity at 1% err, grad vs plain",
         "value": head.pop("value"),
@@ -468,11 +475,14 @@ def main():
     out.update(head)
     if not args.no_extras:
         out["homogeneous_batch"] = homogeneous_batch(max_steps=args.hom_max_steps)
-        out["grad_vs_plain"] = grad_vs_plain(args.lmala_h, args.gvp_max_steps)
+        progress("homogeneous batch done")
+        out["grad_vs_plain"] = grad_vs_plain(args.lmala_h, args.gvp_max_steps, tree_h=args.tree_h)
+        progress("grad-vs-plain leg done")
     if args.occupancy_probe:
         out["occupancy_probe"] = occupancy_probe()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+        progress("cpu baseline done")
     print(json.dumps(out), flush=True)
 
 

@@ -146,7 +146,7 @@ def main():
     ap.add_argument("--chains-per-target", type=int, default=512)
     ap.add_argument("--sources", type=int, default=50)
     args = ap.parse_args()
-    w = W.config5(chains_per_target=args.chains_per_target, n_sources=args.sources)
+    w = W.string_calibration(chains_per_target=args.chains_per_target, n_sources=args.sources)
     rep = fit(w, iters=args.iters, lr=args.lr,
               log=lambda h: print(json.dumps(h), flush=True))
     rep.pop("final_theta")

@@ -157,19 +157,19 @@ def single_target(distance=10.0, radius=0.165, lam_s=25.0, lam_a=100.0, g=0.9,
     return w
 
 
-def config1(**over):
+def reference_target(**over):
     """Plain RJMCMC, FP64: isotropic point source, homogeneous medium
     (scattering length 25 m, absorption length 100 m, g = 0.9), one sensor of
     radius 0.165 m at 10 m, 64 chains x 1e4 steps, cap 64, mix 60/20/20,
     sigma = 1 m, Philox seed 0."""
     w = single_target(10.0, 0.165, 25.0, 100.0, 0.9, chains=64, cap=64, seed=0)
-    w["name"] = "config1"
+    w["name"] = "reference_target"
     w["precision"] = "f64"
     w.update(over)
     return w
 
 
-def config2(seed=1, groups=256, per_group=256, steps=10_000, cap=256, **over):
+def homogeneous_groups(seed=1, groups=256, per_group=256, steps=10_000, cap=256, **over):
     """Batched plain RJMCMC, FP32 evaluation: 256 chain-groups of 256 chains;
     per group a homogeneous medium (scattering length log-U[10,50] m,
     absorption length log-U[50,200] m, g ~ U[0.8,0.95]) and a sensor of
@@ -187,7 +187,7 @@ def config2(seed=1, groups=256, per_group=256, steps=10_000, cap=256, **over):
     n, init = _straight_start(src, sensor, r)
     tg = _targets(np.arange(groups), src, sensor, r, np.zeros(groups, np.int32), np.tile([0, 0, 1.0], (groups, 1)),
                   np.zeros(groups), n, init)
-    w = dict(name="config2", cap=int(cap), **media, **tg,
+    w = dict(name="homogeneous_groups", cap=int(cap), **media, **tg,
              c_target=np.repeat(np.arange(groups, dtype=np.int32), per_group))
     w.update(DEFAULT_RUN)
     w.update(seed=seed, steps=steps, burn_in=steps // 10, precision="f32")
@@ -242,20 +242,20 @@ def layered_pairs(seed=3, pairs=1000, chains=1 << 20, cap=512, steps=10_000,
     return w
 
 
-def config3(**over):
+def layered_batch(**over):
     """Layered medium, ragged batch: 100 layers of 10 m, 1000 cone-source
     pairs at 10-150 m, 2^20 chains, cap 512."""
     w = layered_pairs(seed=3, pairs=1000, chains=1 << 20, cap=512)
-    w["name"] = "config3"
+    w["name"] = "layered_batch"
     w.update(over)
     return w
 
 
-def config4(**over):
-    """Config 3's medium and geometry with 262,144 chains and the
+def layered_batch_langevin(**over):
+    """The layered batch's medium and geometry with 262,144 chains and the
     gradient-informed (MALA) sampler."""
     w = layered_pairs(seed=3, pairs=1000, chains=262_144, cap=512)
-    w.update(name="config4", sampler=1)
+    w.update(name="layered_batch_langevin", sampler=1)
     w.update(over)
     return w
 
@@ -297,7 +297,7 @@ def array_strings(rows=2, per_row=5, spacing=125.0, sensors=60, dz=17.0, zc=500.
     return xy, z
 
 
-def config5(seed=5, n_sources=50, reach=200.0, chains_per_target=512, cap=512, steps=4000, n_layers=100,
+def string_calibration(seed=5, n_sources=50, reach=200.0, chains_per_target=512, cap=512, steps=4000, n_layers=100,
             dz=10.0, sources=None, max_targets=None):
     """Calibration-shaped batch: 10 vertical strings (two rows of five, 125 m
     apart on a triangular lattice) of 60 sensors at 17 m spacing (radius
@@ -331,7 +331,7 @@ def config5(seed=5, n_sources=50, reach=200.0, chains_per_target=512, cap=512, s
     n, init = _straight_start(src, sen, r)
     tg = _targets(np.zeros(T), src, sen, r, np.zeros(T, np.int32), np.tile([0, 0, 1.0], (T, 1)), np.zeros(T),
                   n, init)
-    w = dict(name="config5", cap=int(cap), **media, **tg,
+    w = dict(name="string_calibration", cap=int(cap), **media, **tg,
              c_target=np.repeat(np.arange(T, dtype=np.int32), chains_per_target), t_source_sensor=src_idx)
     w.update(DEFAULT_RUN)
     w.update(seed=seed, steps=steps, burn_in=steps // 10, precision="f32")

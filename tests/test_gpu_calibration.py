@@ -67,7 +67,7 @@ def test_near_targets_intensity_and_gradient_vs_oracle(rj):
     combined standard errors of the oracle's, and d log I / d lambda per layer
     within 3 combined standard errors + 2% wherever the oracle's estimate is
     significant (4 copies of each target on the device give its spread)."""
-    base = W.config5(sources=[SOURCE], chains_per_target=1, max_targets=4, cap=128)
+    base = W.string_calibration(sources=[SOURCE], chains_per_target=1, max_targets=4, cap=128)
     copies = 4
     w = _replicate(base, copies, 8192)
     w["burn_in"] = 0
@@ -111,7 +111,7 @@ def test_fit_lowers_the_loss(rj):
     two-flasher cut of the batch: the chi-square loss in log I drops below 40%
     of its start and the rms log-intensity residual by at least a third."""
     from paper_1811_04156_amd import calibration as K
-    w = W.config5(sources=[SOURCE, 400], chains_per_target=2048)
+    w = W.string_calibration(sources=[SOURCE, 400], chains_per_target=2048)
     rep = K.fit(w, iters=12, lr=0.05)
     h = rep["history"]
     for r in h:

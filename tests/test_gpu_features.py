@@ -46,7 +46,7 @@ def test_graph_replays_match_eager_runs(rj):
     """A captured chunk (sampler steps + score pass) replayed three times,
     with eager work and synchronisations between replays, reproduces three
     eager calls: same paths and counts, FP64 sums to rounding."""
-    w = W.config2(groups=8, per_group=256)
+    w = W.homogeneous_groups(groups=8, per_group=256)
     w["burn_in"] = 0
     eager = rj.Sampler(w, precision="f32")
     graph = rj.Sampler(w, precision="f32")
@@ -96,7 +96,7 @@ def test_fp32_intensity_within_1pct_and_3sigma_of_oracle(rj):
     (FP64, 512 chains per target, its own independent random streams) agree
     within 1% and within 3 combined standard errors, target by target."""
     from oracle import oracle as O
-    w = W.config2(groups=256, per_group=1)
+    w = W.homogeneous_groups(groups=256, per_group=1)
     pick = [int(t) for t in np.argsort(np.linalg.norm(w["t_sensor"], axis=1))[:6]]
     wg = dict(w)
     wg["c_target"] = np.repeat(np.array(pick, np.int32), 16384)
@@ -182,7 +182,7 @@ def test_tilt_kernel_follows_its_rule(rj):
     log(h(mode) / h(n)) for n0 <= n < mode (floor_push where h(n) = 0) and
     clamps to [0, max_logw]; replayed here in numpy from the returned
     histogram of the last round, and the chain statistics are untouched."""
-    w = W.config2(groups=16, per_group=256, cap=64)
+    w = W.homogeneous_groups(groups=16, per_group=256, cap=64)
     w["burn_in"] = 0
     s = rj.Sampler(w, precision="f32")
     s.run(200)

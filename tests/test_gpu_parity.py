@@ -77,10 +77,10 @@ def test_logp_and_gradient_parity(rj, prec, nmax, cap):
 
 @pytest.mark.parametrize("birth_frac", [0.5, 0.3])
 def test_fp64_free_run_matches_oracle(rj, birth_frac):
-    """Config 1 (FP64): the device run and the oracle take the same decisions
+    """The reference single target (FP64): the device run and the oracle take the same decisions
     step by step, end in the same paths and accumulate the same statistics
     (and with an uneven birth/death mix, whose probabilities then enter log A)."""
-    w = W.config1(burn_in=300, birth_frac=birth_frac)
+    w = W.reference_target(burn_in=300, birth_frac=birth_frac)
     steps = 2000
     s = rj.Sampler(w, precision="f64")
     tr, _ = s.run(steps, trace=True)
@@ -308,7 +308,7 @@ def test_default_launch_at_two_waves_per_simd(rj, kind):
     256-chain blocks with fewer LDS slots; the chains must follow exactly the
     trajectories of the one-wave launch (64-chain blocks, 32 slots)."""
     if kind == "homog":
-        w = W.config2(groups=256, per_group=512, cap=64)
+        w = W.homogeneous_groups(groups=256, per_group=512, cap=64)
     else:
         w = W.layered_pairs(pairs=64, chains=1 << 17, cap=64)
     w["burn_in"] = 0
@@ -375,13 +375,13 @@ def test_cap_is_respected(rj):
     assert stats[:, 12].sum() > 0  # the cap is visited and counted
 
 
-@pytest.mark.parametrize("which", ["config2", "config3"])
+@pytest.mark.parametrize("which", ["homogeneous_groups", "layered_batch"])
 def test_full_size_sampled(rj, which):
     """The full chain counts (65,536 chains at cap 256; 2^20 chains over 1000
     layered pairs at cap 512) in the default launch: sampled chains' paths
     re-evaluated by the oracle to 1e-4, cached log p drift, invariants over
     all chains."""
-    w = W.config2() if which == "config2" else W.config3()
+    w = W.homogeneous_groups() if which == "homogeneous_groups" else W.layered_batch()
     s = rj.Sampler(w, precision="f32")
     s.run(500)
     torch.cuda.synchronize()

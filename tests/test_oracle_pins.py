@@ -330,7 +330,7 @@ def test_step_scale_invariance(oracle_mod):
 
 
 def test_step_trace_is_deterministic_and_consistent(oracle_mod):
-    w = W.config1(burn_in=0)
+    w = W.reference_target(burn_in=0)
     orc = oracle_mod.Oracle(w)
     st = oracle_mod.initial_state(w)
     st2 = {k: v.copy() for k, v in st.items()}
@@ -347,7 +347,7 @@ def test_step_trace_is_deterministic_and_consistent(oracle_mod):
 
 
 def test_single_step_matches_run(oracle_mod):
-    w = W.config1(burn_in=0)
+    w = W.reference_target(burn_in=0)
     orc = oracle_mod.Oracle(w)
     st = oracle_mod.initial_state(w, chains=4)
     ref = {k: v.copy() for k, v in st.items()}

@@ -45,7 +45,7 @@ def test_noalloc_intensity_matches_intensity(rj):
     s.run(400)
     _check(s, 16, pass_anchor=False)
     # second call, smaller input: 8 homogeneous targets x 128 chains, caller's anchors
-    w2 = W.config2(groups=8, per_group=128, cap=32)
+    w2 = W.homogeneous_groups(groups=8, per_group=128, cap=32)
     w2["burn_in"] = 50
     s2 = rj.Sampler(w2, precision="f32")
     s2.run(300)
@@ -56,7 +56,7 @@ def test_noalloc_intensity_matches_intensity(rj):
 
 
 def test_noalloc_rejects_inputs_beyond_its_buffer(rj):
-    w = W.config2(groups=1400, per_group=1, cap=16)
+    w = W.homogeneous_groups(groups=1400, per_group=1, cap=16)
     s = rj.Sampler(w, precision="f32")
     with pytest.raises(rj.RJPathError, match="exceeds its static buffer"):
         s.intensity_noalloc(groups=64)
