@@ -264,9 +264,17 @@ __device__ __forceinline__ void seg_depth_lp(const Tgt<R>& T, LPt P, LPt Q, R le
     const double Ic = (double)ac * (eh - lo) + (pl.x - ph.x) + (double)b[LY_C] * (hi - el);
     const double Ib = (double)ab * (eh - lo) + (pl.y - ph.y) + (double)b[LY_B] * (hi - el);
     const bool same = P.l == Q.l;
-    const double inv = 1.0 / (same ? 1.0 : hi - lo);
-    tc = same ? ac * len : (R)(Ic * inv) * len;
-    tb = same ? ab * len : (R)(Ib * inv) * len;
+    if constexpr (sizeof(R) == 4) {
+        // the quotient is rounded to FP32 anyway: an FP32 reciprocal of the
+        // FP64 difference (rounded once) instead of an FP64 division
+        const R ir = Mth<R>::rcp((R)(same ? 1.0 : hi - lo));
+        tc = same ? ac * len : (R)Ic * ir * len;
+        tb = same ? ab * len : (R)Ib * ir * len;
+    } else {
+        const double inv = 1.0 / (same ? 1.0 : hi - lo);
+        tc = same ? ac * len : (R)(Ic * inv) * len;
+        tb = same ? ab * len : (R)(Ib * inv) * len;
+    }
 }
 
 // log of the per-steradian scattering function at a vertex with incoming and

@@ -497,7 +497,7 @@ template <class R> __device__ __forceinline__ void fold_hist(Lane<R>& ln, const 
 // The move draws a von Mises-Fisher step of the end point on the sensor
 // (words 4, 5, as the end-point perturbation) and Gaussian steps of variance
 // mala_h / n for every (zeta, t, phi) (vertex m: one Philox block with
-// counter word 3 = 2 + m), builds the proposal top-down level by level (each
+// counter word 3 = 2 + m), builds the proposal node by node in pre-order (each
 // vertex's foci and frame come from vertices placed before it) into the work
 // buffer, and accepts with
 //   log A = log p(y) - log p(x) + sum_m [log J_m(y) - log J_m(x)],
@@ -520,7 +520,9 @@ template <class R> struct TreePath {
         const bool s0 = v == 0, se = v == n - 1;
         return {s0 ? y0.x : (se ? yend.x : g.x), s0 ? y0.y : (se ? yend.y : g.y), s0 ? y0.z : (se ? yend.z : g.z)};
     }
-    __device__ __forceinline__ void stw(int, R) const {}
+    // the y walk's segment depths are kept in the work buffer (slot v: the
+    // segment leaving vertex v) for the copy-back on acceptance
+    __device__ __forceinline__ void stw(int v, R x) const { work.glb[(size_t)v * work.C].w = x; }
 };
 
 // frame (e2, e3) of interval (k, l) of a path: root -> onb of the axis;
@@ -572,24 +574,29 @@ __device__ __forceinline__ void tree_move(const Tgt<R>& T, const PathRef<R, LO>&
     const R sig = Mth<R>::sqrt((R)sc.mala_h / (R)n);
     double lj = 0.0; // sum of log J(y) - log J(x)
     bool ok = true;
-    for (int d = 0;; ++d) {
-        bool any = false;
-        for (int j = 0; j < (1 << d); ++j) {
-            // interval of node (d, j) and of its parent, by descent from the root
-            int k = 0, l = n - 1, kp = 0, lp = n - 1;
-            for (int b = d - 1; b >= 0; --b) {
+    // Nodes in pre-order (a node before its subtrees, so every vertex's foci
+    // and frame are placed before it): node i is found by descending from the
+    // root, skipping whole left subtrees by their vertex count.  A lane visits
+    // its n - 2 nodes only.
+    for (int i = 0; i < n - 2; ++i) {
+        {
+            int k = 0, l = n - 1, kp = 0, lp = n - 1, left = i;
+            bool root = true;
+            for (;;) {
                 const int mid = (k + l) >> 1;
+                if (left == 0) break;
+                left -= 1; // the node itself
                 kp = k;
                 lp = l;
-                if ((j >> b) & 1)
-                    k = mid;
-                else
+                root = false;
+                if (left < mid - k - 1) {
                     l = mid;
+                } else {
+                    left -= mid - k - 1;
+                    k = mid;
+                }
             }
-            if (l - k < 2) continue;
-            any = true;
             const int m = (k + l) >> 1, pm = (kp + lp) >> 1;
-            const bool root = d == 0;
             // current coordinates of x_m
             const V3<R> xk = xat(k), xl = xat(l), xm = xat(m);
             const V3<R> rx = xl - xk;
@@ -640,18 +647,19 @@ __device__ __forceinline__ void tree_move(const Tgt<R>& T, const PathRef<R, LO>&
             ok = ok && isfinite(ym.x) && isfinite(ym.y) && isfinite(ym.z);
             work.glb[(size_t)m * work.C] = Vtx<R>{ym.x, ym.y, ym.z, (R)0};
         }
-        if (!any) break;
     }
-    double L;
-    const double lpx = full_logp(T, ps, n, L);
-    const double lpy = ok ? full_logp(T, yp, n, L) : -__builtin_inf();
+    double Lx, Ly = 0.0;
+    const double lpx = full_logp(T, ps, n, Lx);
+    const double lpy = ok ? full_logp(T, yp, n, Ly) : -__builtin_inf();
     const double la = lpy - lpx + lj;
     logA = isfinite(lpy) && isfinite(la) ? (R)la : Mth<R>::ninf();
     if (logu < logA) {
         accepted = 1;
+        // the proposal with the depths its walk left in the work buffer
         for (int k = 1; k <= n - 2; ++k) ps.st(k, work.ld(k));
+        ps.stw(0, work.ld(0).w);
         ps.st(n - 1, Vtx<R>{yend.x, yend.y, yend.z, (R)0});
-        full_logp(T, ps, n, ln.L); // refresh the cached depths and L
+        ln.L = Ly;
     }
 }
 
