@@ -338,6 +338,26 @@ int rjpath_length_hist(rjpath_medium* m, const rjpath_targets* t, const rjpath_c
 int rjpath_grad(rjpath_medium* m, const rjpath_targets* t, const rjpath_chains* c, double* logp_out,
                 void* dlogp_dv, double* score, void* stream);
 
+/* Length-weighted score sums of the current paths, for the gradient of the
+ * mean path length (the arrival-time delay that constrains scattering, Sec.
+ * "Comparison of timing distributions"): score_L (device, n_targets *
+ * (1 + 3 * L_total) doubles, the layout of rjpath_grad's score) is ADDED to:
+ * [t][0] += L_c / w(n_c) and [t][1 + 3 l + k] += (L_c / w(n_c)) d log p / d theta_{l,k}
+ * over the chains of target t with status 0, where L_c is the path length.
+ * Asynchronous on `stream`; allocates nothing. */
+int rjpath_score_length(rjpath_medium* m, const rjpath_targets* t, const rjpath_chains* c, double* score_L,
+                        void* stream);
+
+/* Mean path length m_t = E_p[L] = score_L[t][0] / score[t][0] and its gradient
+ * d m_t / d theta_j = E_p[L s_j] - E_p[L] E_p[s_j] (s = d log p / d theta, the
+ * derivative of a normalised expectation) from the sums of rjpath_grad (score)
+ * and rjpath_score_length (score_L) accumulated over the same paths.
+ * mean_L: device, n_targets doubles (may be NULL); dmean_L: device,
+ * n_targets * 3 L_total doubles (theta = lambda_s, lambda_a, g per global
+ * layer); NaN for a target without samples.  Asynchronous on `stream`. */
+int rjpath_dlength_dtheta(rjpath_medium* m, const rjpath_targets* t, const double* score, const double* score_L,
+                          double* mean_L, double* dmean_L, void* stream);
+
 /* Sector-tilt tuning (the tilt w(n) of the anchored estimator; the estimator
  * undoes it, so any tilt leaves the intensity unchanged, but a flat sector
  * histogram lets distant targets visit the anchor sector n0 often).

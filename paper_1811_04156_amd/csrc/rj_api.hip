@@ -604,8 +604,29 @@ int rjpath_grad(rjpath_medium* m, const rjpath_targets* t, const rjpath_chains* 
     int r = check_common(m, t, c);
     if (r) return r;
     KArgs a = make_args(m, t, c);
-    hipError_t e = launch_grad(a, logp_out, dlogp_dv, score, m->L_total, (hipStream_t)stream);
+    hipError_t e = launch_grad(a, logp_out, dlogp_dv, score, m->L_total, 0, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "grad kernel launch");
+    return RJPATH_OK;
+}
+
+int rjpath_score_length(rjpath_medium* m, const rjpath_targets* t, const rjpath_chains* c, double* score_L,
+                        void* stream) {
+    int r = check_common(m, t, c);
+    if (r) return r;
+    if (!score_L) return fail(RJPATH_EINVAL, "null score_L");
+    KArgs a = make_args(m, t, c);
+    hipError_t e = launch_grad(a, nullptr, nullptr, score_L, m->L_total, 1, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "grad kernel launch");
+    return RJPATH_OK;
+}
+
+int rjpath_dlength_dtheta(rjpath_medium* m, const rjpath_targets* t, const double* score, const double* score_L,
+                          double* mean_L, double* dmean_L, void* stream) {
+    int r = check_targets(m, t);
+    if (r) return r;
+    if (!score || !score_L || !dmean_L) return fail(RJPATH_EINVAL, "null score, score_L or dmean_L");
+    HIPCHK(launch_dlength(t->n_targets, 3 * m->L_total, score, score_L, mean_L, dmean_L, (hipStream_t)stream),
+           "dlength kernel launch");
     return RJPATH_OK;
 }
 

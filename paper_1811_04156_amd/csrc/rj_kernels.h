@@ -29,7 +29,12 @@ RJ_RUN_EXTERN(double, 1)
 RJ_RUN_EXTERN(double, 2)
 RJ_RUN_EXTERN(double, 3)
 #undef RJ_RUN_EXTERN
-hipError_t launch_grad(const KArgs& a, double* logp_out, void* dv, double* score, int L_total, hipStream_t s);
+// lweight: weight each path's score by its length (the sums of rjpath_score_length)
+hipError_t launch_grad(const KArgs& a, double* logp_out, void* dv, double* score, int L_total, int lweight,
+                       hipStream_t s);
+// dm[T * P] = sL[t][1 + j] / sc[t][0] - (sL[t][0] / sc[t][0]) (sc[t][1 + j] / sc[t][0]); m[T] = sL[t][0] / sc[t][0]
+hipError_t launch_dlength(int T, int P, const double* score, const double* score_L, double* m, double* dm,
+                          hipStream_t s);
 // *counter += steps on the device (keeps captured graphs advancing)
 hipError_t launch_advance(uint64_t* counter, uint64_t steps, hipStream_t s);
 // I_{n0} per target into anchor[T] (device).  `lay64` is the FP64 layer table.

@@ -16,7 +16,7 @@ namespace rj {
 // ---------------------------------------------------------------------------
 template <class R>
 __global__ void __launch_bounds__(256) grad_kernel(KArgs a, double* logp_out, Vtx<R>* dv, double* score,
-                                                   int L_total, int lds_rows) {
+                                                   int L_total, int lds_rows, int lweight) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int tmin_s[4], tmax_s[4];
     double* tab = (double*)smem;
@@ -55,7 +55,16 @@ __global__ void __launch_bounds__(256) grad_kernel(KArgs a, double* logp_out, Vt
         if (score && isfinite(lp) && a.status[c] == 0) {
             const int off = a.minfo[a.medium[t]].off;
             const double* logw = a.logw ? a.logw + (size_t)t * (a.cap + 1) : nullptr;
-            const double iw = logw ? exp(-logw[n]) : 1.0;
+            double iw = logw ? exp(-logw[n]) : 1.0;
+            if (lweight) {
+                // weight by the path length (FP64 sum of the segment lengths)
+                double Lp = 0.0;
+                for (int k = 1; k < n; ++k) {
+                    const V3<R> d = ps.p(k) - ps.p(k - 1);
+                    Lp += sqrt((double)dot(d, d));
+                }
+                iw *= Lp;
+            }
             double* sc = local ? tab + (size_t)(t - tmin) * row : score + (size_t)t * row;
             atomicAdd(sc, iw);
             // d/d lambda_s = -b^2 d/db, d/d lambda_a = -a^2 d/da, with d log p/da = -L_l and
@@ -150,7 +159,8 @@ hipError_t launch_advance(uint64_t* counter, uint64_t steps, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_grad(const KArgs& a, double* logp_out, void* dv, double* score, int L_total, hipStream_t s) {
+hipError_t launch_grad(const KArgs& a, double* logp_out, void* dv, double* score, int L_total, int lweight,
+                       hipStream_t s) {
     int block = 256, grid = (a.C + block - 1) / block;
     // LDS table for two targets per block when it fits in 64 KiB
     const size_t row_bytes = sizeof(double) * (1 + 3 * (size_t)L_total);
@@ -158,10 +168,10 @@ hipError_t launch_grad(const KArgs& a, double* logp_out, void* dv, double* score
     const size_t lds = rows * row_bytes;
     if (a.prec == RJPATH_F64)
         hipLaunchKernelGGL(grad_kernel<double>, dim3(grid), dim3(block), lds, s, a, logp_out, (Vtx<double>*)dv, score,
-                           L_total, rows);
+                           L_total, rows, lweight);
     else
         hipLaunchKernelGGL(grad_kernel<float>, dim3(grid), dim3(block), lds, s, a, logp_out, (Vtx<float>*)dv, score,
-                           L_total, rows);
+                           L_total, rows, lweight);
     return hipGetLastError();
 }
 

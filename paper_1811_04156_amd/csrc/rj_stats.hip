@@ -116,6 +116,23 @@ __global__ void dlogi_kernel(int T, int P, const double* score, double* dlogI) {
     dlogI[i] = z > 0 ? score[t * (1 + P) + 1 + j] / z : __builtin_nan("");
 }
 
+// mean path length m = E_p[L] and d m / d theta_j = E_p[L s_j] - E_p[L] E_p[s_j]
+// (s = d log p / d theta) from the plain and the length-weighted score sums
+__global__ void dlength_kernel(int T, int P, const double* score, const double* score_L, double* m, double* dm) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)T * P) return;
+    const size_t t = i / P, j = i % P;
+    const double z = score[t * (1 + P)];
+    if (!(z > 0)) {
+        dm[i] = __builtin_nan("");
+        if (j == 0 && m) m[t] = __builtin_nan("");
+        return;
+    }
+    const double mt = score_L[t * (1 + P)] / z;
+    dm[i] = score_L[t * (1 + P) + 1 + j] / z - mt * (score[t * (1 + P) + 1 + j] / z);
+    if (j == 0 && m) m[t] = mt;
+}
+
 __global__ void fill_u32_kernel(uint32_t* p, size_t n, uint32_t v) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
 }
@@ -145,6 +162,14 @@ hipError_t launch_dlogi(int T, int P, const double* score, double* dlogI, hipStr
     const size_t n = (size_t)T * P;
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(dlogi_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, T, P, score, dlogI);
+    return hipGetLastError();
+}
+
+hipError_t launch_dlength(int T, int P, const double* score, const double* score_L, double* m, double* dm,
+                          hipStream_t s) {
+    const size_t n = (size_t)T * P;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(dlength_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, T, P, score, score_L, m, dm);
     return hipGetLastError();
 }
 

@@ -56,7 +56,7 @@ class Proposal(C.Structure):
 EXPORTS = ["rjpath_last_error", "rjpath_version", "rjpath_init_medium", "rjpath_free_medium", "rjpath_run_chains",
            "rjpath_anchor", "rjpath_intensity", "rjpath_grad", "rjpath_autotune", "rjpath_tune_tilt", "rjpath_dlogi_dtheta",
            "rjpath_intensity_noalloc", "rjpath_yield_accumulate", "rjpath_yield", "rjpath_length_hist",
-           "rjpath_tune_proposal"]
+           "rjpath_tune_proposal", "rjpath_score_length", "rjpath_dlength_dtheta"]
 
 _lib = None
 
@@ -97,6 +97,8 @@ def load(path: str = LIB_PATH):
                                      _p, _p]
     L.rjpath_tune_proposal.argtypes = [_p, C.POINTER(Targets), C.POINTER(Chains), C.POINTER(RunParams), C.c_int32,
                                        C.POINTER(Proposal), C.c_int32, C.c_int32, _p, C.POINTER(C.c_int32), _p]
+    L.rjpath_score_length.argtypes = [_p, C.POINTER(Targets), C.POINTER(Chains), _p, _p]
+    L.rjpath_dlength_dtheta.argtypes = [_p, C.POINTER(Targets), _p, _p, _p, _p, _p]
     for f in EXPORTS[2:]:
         getattr(L, f).restype = C.c_int
     _lib = L
@@ -457,3 +459,22 @@ class Sampler:
         _check(load().rjpath_length_hist(self.medium.h, C.byref(tg), C.byref(ch), int(bins), float(l0), float(width),
                                          _tp(hist), self._stream_ptr()))
         return hist
+
+    def score_length(self, score_L=None):
+        """Adds the length-weighted score sums of the current paths
+        (rjpath_score_length) into score_L (T, 1 + 3 L_total)."""
+        if score_L is None:
+            score_L = torch.zeros((self.T, 1 + 3 * self.medium.L_total), dtype=torch.float64, device=self.dev)
+        tg, ch = self._targets(), self._chains()
+        _check(load().rjpath_score_length(self.medium.h, C.byref(tg), C.byref(ch), _tp(score_L), self._stream_ptr()))
+        return score_L
+
+    def dlength(self, score, score_L):
+        """Mean path length (T,) and its gradient (T, L_total, 3) from the two
+        score sums (rjpath_dlength_dtheta)."""
+        m = torch.empty(self.T, dtype=torch.float64, device=self.dev)
+        dm = torch.empty((self.T, 3 * self.medium.L_total), dtype=torch.float64, device=self.dev)
+        tg = self._targets()
+        _check(load().rjpath_dlength_dtheta(self.medium.h, C.byref(tg), _tp(score), _tp(score_L), _tp(m), _tp(dm),
+                                            self._stream_ptr()))
+        return m, dm.reshape(self.T, self.medium.L_total, 3)

@@ -106,6 +106,87 @@ def test_near_targets_intensity_and_gradient_vs_oracle(rj):
     print(f"worst relative gradient error among significant entries: {worst:.2%}")
 
 
+def _oracle_length_moments(w, chunks, chunk_steps, burn, groups=16):
+    """The oracle's mean path length m = E_p[L] and d m / d (lambda_s,
+    lambda_a) = E_p[L s] - E_p[L] E_p[s] per target (no tilt, so E_p is the
+    chains' average), each with a standard error over chain groups."""
+    from oracle import oracle as O
+    orc = O.Oracle(w)
+    st = O.initial_state(w)
+    C = len(st["target"])
+    ids = np.arange(C) + 4_000_000
+    orc.run(w, st, burn, step0=0, chain_ids=ids)
+    T = len(w["t_src"])
+    L = int(w["m_layer_cnt"][0])
+    grp = np.arange(C) % groups
+    S0 = np.zeros((T, groups))
+    SL = np.zeros((T, groups))
+    Ss = np.zeros((T, groups, L, 2))
+    SLs = np.zeros((T, groups, L, 2))
+    for k in range(chunks):
+        orc.run(w, st, chunk_steps, step0=burn + k * chunk_steps, chain_ids=ids)
+        for c in range(C):
+            t, g = int(st["target"][c]), grp[c]
+            x = st["verts"][c, : st["n"][c]]
+            Lc = float(np.linalg.norm(np.diff(x, axis=0), axis=1).sum())
+            _, ds, da, _ = orc.grad(t, x)
+            sc = np.stack([ds, da], axis=1)
+            S0[t, g] += 1
+            SL[t, g] += Lc
+            Ss[t, g] += sc
+            SLs[t, g] += Lc * sc
+
+    def est(s0, sl, ss, sls):
+        m = sl / s0
+        return m, sls / s0 - m * (ss / s0)
+
+    m, dm = est(S0.sum(1), SL.sum(1), Ss.sum(1), SLs.sum(1))
+    per = [est(S0[:, g], SL[:, g], Ss[:, g], SLs[:, g]) for g in range(groups)]
+    mse = np.std([p[0] for p in per], axis=0, ddof=1) / np.sqrt(groups)
+    dmse = np.std([p[1] for p in per], axis=0, ddof=1) / np.sqrt(groups)
+    return m, mse, dm, dmse
+
+
+def test_mean_length_and_its_gradient_vs_oracle(rj):
+    """rjpath_score_length + rjpath_dlength_dtheta: the mean path length of
+    the detected light and d m / d (lambda_s, lambda_a) per layer on the two
+    17 m targets of one flasher agree with the oracle's estimates within 3
+    combined standard errors + 1% wherever the oracle's gradient entry is
+    significant (4 device copies give the device's spread)."""
+    base = W.string_calibration(sources=[SOURCE], chains_per_target=1, max_targets=2, cap=128)
+    copies = 4
+    w = _replicate(base, copies, 8192)
+    w["burn_in"] = 0
+    s = rj.Sampler(w, precision="f32")
+    s.run(2000)
+    P = 1 + 3 * s.medium.L_total
+    score = torch.zeros((s.T, P), dtype=torch.float64, device=s.dev)
+    score_L = torch.zeros_like(score)
+    for _ in range(20):
+        s.run(200)
+        s.grad(logp=False, score=score)
+        s.score_length(score_L)
+    m, dm = s.dlength(score, score_L)
+    m = m.cpu().numpy().reshape(copies, 2)
+    dm = dm.cpu().numpy()[:, :, :2].reshape(copies, 2, -1, 2)
+    md, mse_d = m.mean(0), m.std(0, ddof=1) / math.sqrt(copies)
+    dd, dse_d = dm.mean(0), dm.std(0, ddof=1) / math.sqrt(copies)
+    wo = dict(base)
+    wo["c_target"] = np.repeat(np.arange(2, dtype=np.int32), 1024)
+    wo["burn_in"] = 0
+    mo, mse_o, do, dse_o = _oracle_length_moments(wo, chunks=40, chunk_steps=300, burn=2000)
+    for t in range(2):
+        sig = math.hypot(mse_d[t], mse_o[t])
+        sel = np.abs(do[t]) > 4 * dse_o[t]
+        sig_d = np.hypot(dse_d[t], dse_o[t])
+        err = np.abs(dd[t] - do[t])
+        print(f"target {t}: mean length device {md[t]:.5f} m, oracle {mo[t]:.5f} +- {mse_o[t]:.5f}; "
+              f"{sel.sum()} significant gradient entries, max |z| {np.max(err[sel] / sig_d[sel]) if sel.any() else 0:.2f}")
+        assert abs(md[t] - mo[t]) < 3 * sig + 1e-4 * mo[t]
+        assert sel.sum() >= 2
+        assert np.all(err[sel] < 3 * sig_d[sel] + 0.01 * np.abs(do[t][sel]))
+
+
 def test_fit_lowers_the_loss(rj):
     """Gradient fit (Adam on log lambda) from the seeded perturbed start on a
     two-flasher cut of the batch: the chi-square loss in log I drops below 40%
