@@ -90,14 +90,16 @@ template <class R> struct GlobalPath {
 };
 
 // Full log p of the path (FP64 sum of the factors), refreshing the cached
-// segment scattering depths; also returns the path length L.
+// segment scattering depths; also returns the path length L and, where Sb is
+// given, the FP64 sum of the refreshed depths in path order.
 template <class R, class P>
-__device__ __forceinline__ double full_logp(const Tgt<R>& T, const P& ps, int n, double& L) {
+__device__ __forceinline__ double full_logp(const Tgt<R>& T, const P& ps, int n, double& L, double* Sb = nullptr) {
     V3<R> f0 = ps.p(0), f1 = ps.p(1);
     Seg<R> s = make_seg(T, f0, f1);
     bool zero = !(s.len > (R)0);
     double lp = (double)emit_term(T, s.u) + (double)seg_term(s);
     L = (double)s.len;
+    double sb = (double)s.tb;
     ps.stw(0, s.tb);
     V3<R> fc = f1;
     for (int k = 1; k <= n - 2; ++k) {
@@ -107,12 +109,14 @@ __device__ __forceinline__ double full_logp(const Tgt<R>& T, const P& ps, int n,
         const LayV<R> ly = lay_of(T, fc);
         lp += (double)(ly.logb + turn_term(ly, s.u, s2.u)) + (double)seg_term(s2);
         L += (double)s2.len;
+        sb += (double)s2.tb;
         ps.stw(k, s2.tb);
         s = s2;
         fc = fn;
     }
     lp += (double)end_term(T, s.u, fc);
     if (zero) lp = -__builtin_inf();
+    if (Sb) *Sb = sb;
     return lp;
 }
 
@@ -447,6 +451,7 @@ template <class R> struct Lane {
     int n;
     bool live; // the chain steps (a malformed or zero-density chain keeps its state)
     double L;    // path length (running sum; refreshed at launch start)
+    double S;    // sum of the cached segment scattering depths (running sum; refreshed at launch start)
     double lp;   // log p (refreshed at launch start and end)
     double invw; // 1 / w(n) of the sector tilt
     double lwm, lw0, lwp; // log w(n - 1), log w(n), log w(n + 1)
@@ -648,9 +653,9 @@ __device__ __forceinline__ void tree_move(const Tgt<R>& T, const PathRef<R, LO>&
             work.glb[(size_t)m * work.C] = Vtx<R>{ym.x, ym.y, ym.z, (R)0};
         }
     }
-    double Lx, Ly = 0.0;
+    double Lx, Ly = 0.0, Sy = 0.0;
     const double lpx = full_logp(T, ps, n, Lx);
-    const double lpy = ok ? full_logp(T, yp, n, Ly) : -__builtin_inf();
+    const double lpy = ok ? full_logp(T, yp, n, Ly, &Sy) : -__builtin_inf();
     const double la = lpy - lpx + lj;
     logA = isfinite(lpy) && isfinite(la) ? (R)la : Mth<R>::ninf();
     if (logu < logA) {
@@ -660,6 +665,7 @@ __device__ __forceinline__ void tree_move(const Tgt<R>& T, const PathRef<R, LO>&
         ps.stw(0, work.ld(0).w);
         ps.st(n - 1, Vtx<R>{yend.x, yend.y, yend.z, (R)0});
         ln.L = Ly;
+        ln.S = Sy;
     }
 }
 
@@ -757,7 +763,7 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
             if (logu < logA) {
                 accepted = 1;
                 for (int k = 1; k <= n - 2; ++k) ps.st(k, work.ld(k));
-                full_logp(T, ps, n, ln.L); // refresh the cached depths and L
+                full_logp(T, ps, n, ln.L, &ln.S); // refresh the cached depths, L and S
             }
             return;
         }
@@ -766,7 +772,8 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
         // slots j-2 .. j+2 (absent neighbours are replaced by stand-ins below;
         // in LDS their slots are readable as they are, elsewhere the indices
         // are clamped to stay in range)
-        const V3<R> gm2 = ps.p(LO || hm2 ? j - 2 : 0), fm1 = ps.p(j - 1), fo = ps.p(j);
+        const Vtx<R> vm1 = ps.ld(j - 1), vo = ps.ld(j);
+        const V3<R> gm2 = ps.p(LO || hm2 ? j - 2 : 0), fm1 = pos(vm1), fo = pos(vo);
         const V3<R> gp1 = ps.p(LO || hp1 ? j + 1 : 0), gp2 = ps.p(LO || hp2 ? j + 2 : 0);
         const V3<R> fm2 = hm2 ? gm2 : fm1 - ex;
         const V3<R> fp1 = hp1 ? gp1 : fo + ex;
@@ -842,29 +849,22 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
             ps.st(j, Vtx<R>{fn.x, fn.y, fn.z, hp1 ? Bn.tb : (R)0});
             ps.stw(j - 1, An.tb);
             ln.L += (double)An.len - (double)Ao.len + (hp1 ? (double)Bn.len - (double)Bo.len : 0.0);
+            ln.S += ((double)An.tb - (double)vm1.w) + (hp1 ? (double)Bn.tb - (double)vo.w : 0.0);
         }
         return;
     }
     // ---------- birth / death through the bi-spherical map ----------
     const bool birth = r[2] < sc.bthresh;
     move = birth ? MV_BIRTH : MV_DEATH;
-    // S = sum of the cached segment depths, summed afresh in a fixed order (so
-    // the chain does not depend on where launches start and end).  The first
-    // WB depths are read once into registers (loads issued together) and
-    // serve both the sum and the segment scan.
+    // S = sum of the cached segment depths, kept by the lane as a running sum
+    // (summed afresh in path order at every launch start and after whole-path
+    // moves).  The segment scan of a birth reads the first WB depths once into
+    // registers (loads issued together) and the rest four at a time.
     // (16 cover all but rare long paths of the batched workloads; the FP64
     // and Langevin variants keep 8 so that their registers still allow two
     // resident waves per SIMD where they did)
     constexpr int WB = (sizeof(R) == 4 && SAMP == SAMP_PLAIN) ? 16 : 8;
-    R wv[WB];
-#pragma unroll
-    for (int v = 0; v < WB; ++v) wv[v] = ps.w(v < n - 1 ? v : 0);
-#pragma unroll
-    for (int v = 0; v < WB; ++v) wv[v] = v < n - 1 ? wv[v] : (R)0; // (adding 0 leaves a sum unchanged)
-    double S = 0.0;
-#pragma unroll
-    for (int v = 0; v < WB; ++v) S += (double)wv[v];
-    for (int v = WB; v < n - 1; ++v) S += (double)ps.w(v);
+    const double S = ln.S;
     const bool valid = birth ? (n < sc.cap && S > 0.0) : (n > 2);
     int iA = 0, jv = 1;
     if (valid) {
@@ -873,17 +873,27 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
             // cumulative depth exceeds U S, i.e. the number of prefixes that
             // do not (the cumulative sums never decrease)
             const double tgt = (double)unif<double>(r[0]) * S;
+            R wv[WB];
+#pragma unroll
+            for (int v = 0; v < WB; ++v) wv[v] = ps.w(v < n - 1 ? v : 0);
             double cum = 0.0;
             int k = 0;
-            // (past the path the cumulative sum stays at S > U S: no count)
+            // (past the path the cumulative sum stays at S > U S: no count;
+            // once it exceeds U S no later prefix counts either)
 #pragma unroll
             for (int v = 0; v < WB; ++v) {
-                cum += (double)wv[v];
+                cum += v < n - 1 ? (double)wv[v] : 0.0;
                 k += cum <= tgt ? 1 : 0;
             }
-            for (int v = WB; v < n - 1; ++v) {
-                cum += (double)ps.w(v);
-                k += cum <= tgt ? 1 : 0;
+            for (int v = WB; v < n - 1 && cum <= tgt; v += 4) {
+                R w4[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) w4[i] = ps.w(v + i < n - 1 ? v + i : v);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    cum += v + i < n - 1 ? (double)w4[i] : 0.0;
+                    k += cum <= tgt ? 1 : 0;
+                }
             }
             k = k < n - 2 ? k : n - 2;
             iA = k;
@@ -896,20 +906,27 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
     const int iB = birth ? iA + 1 : iA + 2;
     const bool hprev = iA >= 1, hnext = iB + 1 <= n - 1;
     V3<R> A, B, gprev, gnext, fj;
+    R wA, wj; // cached depths of segments iA and jv (jv's is used by a death)
     if (LO) {
         // slots iA-1 .. iA+3, read as they are (padding makes all readable)
-        const V3<R> s0 = ps.p(iA - 1), s1 = ps.p(iA), s2 = ps.p(iA + 1), s3 = ps.p(iA + 2), s4 = ps.p(iA + 3);
+        const Vtx<R> s1 = ps.ld(iA), s2 = ps.ld(iA + 1);
+        const V3<R> s0 = ps.p(iA - 1), s3 = ps.p(iA + 2), s4 = ps.p(iA + 3);
         gprev = s0;
-        A = s1;
-        fj = s2; // jv = iA + 1 for a death (unused by a birth)
-        B = birth ? s2 : s3;
+        A = pos(s1);
+        fj = pos(s2); // jv = iA + 1 for a death (unused by a birth)
+        wA = s1.w;
+        wj = s2.w;
+        B = birth ? pos(s2) : s3;
         gnext = birth ? s3 : s4;
     } else {
-        A = ps.p(iA);
+        const Vtx<R> vA = ps.ld(iA), vj = ps.ld(jv);
+        A = pos(vA);
+        wA = vA.w;
         B = ps.p(iB < n ? iB : n - 1);
         gprev = ps.p(hprev ? iA - 1 : 0);
         gnext = ps.p(hnext ? iB + 1 : 0);
-        fj = ps.p(jv);
+        fj = pos(vj);
+        wj = vj.w;
     }
     const V3<R> fprev = hprev ? gprev : A - ex;
     const V3<R> fnext = hnext ? gnext : B + ex;
@@ -954,7 +971,7 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
     R jac = -sA.tc - sB.tc + AB.tc + (R)2 * Mth<R>::log(sA.len + sB.len) - AB.loglen + qs.lnorm +
             (R)0.5 * beta * q + LOG2PI;
     const int nx = birth ? n : n - 1;
-    const double Sx = birth ? S : S - (double)ps.w(iA) - (double)ps.w(jv) + (double)AB.tb;
+    const double Sx = birth ? S : S - (double)wA - (double)wj + (double)AB.tb;
     R lpup = (R)sc.log_pb + Mth<R>::log(AB.tb) - Mth<R>::log((R)Sx);
     R lpdn = (R)sc.log_pd - Mth<R>::log((R)(nx - 1));
     // logw[nx + 1] - logw[nx] (both differences formed first: a choice between
@@ -973,6 +990,7 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
             ps.st(iB, Vtx<R>{fv.x, fv.y, fv.z, sB.tb});
             ps.stw(iA, sA.tb);
             ln.L += dL;
+            ln.S = (S - (double)wA) + ((double)sA.tb + (double)sB.tb);
             ln.n = n + 1;
             if (sc.logw) {
                 ln.lwm = ln.lw0;
@@ -983,6 +1001,7 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
             for (int v = jv; v <= n - 2; ++v) ps.st(v, ps.ld(v + 1));
             ps.stw(iA, AB.tb);
             ln.L -= dL;
+            ln.S = Sx;
             ln.n = n - 1;
             if (sc.logw) {
                 ln.lwp = ln.lw0;
@@ -1096,7 +1115,7 @@ __global__ void __launch_bounds__(256) run_kernel(KArgs a) {
     const int nl0 = ln.n < a.V ? ln.n : a.V;
     for (int v = 0; v < nl0; ++v) lds_st<R>(ps.lds + v * WAVE, ps.glb[(size_t)v * C]);
 
-    ln.lp = full_logp(T, ps, ln.n, ln.L);
+    ln.lp = full_logp(T, ps, ln.n, ln.L, &ln.S);
     const bool healthy = isfinite(ln.lp);
     a.status[c] = healthy ? 0 : 1;
 
