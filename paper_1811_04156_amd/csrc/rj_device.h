@@ -118,6 +118,12 @@ template <class R> struct Tgt {
     int mcnt, uniform;
     bool sl;      // false: no layer of the medium mixes in the Rayleigh-like term
     double ax, ay, az, e0, inv_h, usrc;
+    // the FP32 layer lookups: the axis rounded, the source's position in layer
+    // units split into its layer lsrc and the fraction fsrc, and 1 / h
+    V3<R> axr;
+    R fsrc, ihr;
+    int lsrc;
+    const MedInfo* mi;   // the medium's axis and spacing (the exact lookups read them here)
     LayV<R> l0;          // layer 0 (the only one of a homogeneous medium)
     const R* lay;        // layer table of this medium (LY_NW per layer), LDS or HBM
     const double* edge;  // edges of this medium (mcnt + 1)
@@ -177,22 +183,24 @@ template <class R> __device__ __forceinline__ LayV<R> lay_of(const Tgt<R>& T, V3
     return ly;
 }
 
-// A point's coordinate along the layer axis (FP64, absolute) and its layer
-// index, computed once per vertex and step and shared by every factor and
-// segment that touches the vertex.
-struct LPt {
-    double u;
+// A point's coordinate along the layer axis and its layer index, computed
+// once per vertex and step and shared by every factor and segment that
+// touches the vertex.  FP64: the absolute coordinate; FP32: the coordinate
+// relative to the source (the vertices' own frame, so that it is as precise
+// as the vertex itself).
+template <class R> struct LPt {
+    R u;
     int l;
 };
 
 // Layer index of axis coordinate u: for uniformly spaced edges the floor of
 // (u - e0) / h, settled against the two stored edges around it without
 // branching (the same index as layer_u).
-template <class R> __device__ __forceinline__ int layer_idx(const Tgt<R>& T, double u) {
+template <class R> __device__ __forceinline__ int layer_idx_s(const Tgt<R>& T, double u, double e0, double inv_h) {
     const int cnt = T.mcnt;
     if (cnt == 1) return 0;
     if (!T.uniform) return layer_u(T, u);
-    double q = floor((u - T.e0) * T.inv_h);
+    double q = floor((u - e0) * inv_h);
     q = fmin(fmax(q, 0.0), (double)(cnt - 1));
     const int l = (int)q;
     const double elo = T.edge[l], ehi = T.edge[l + 1];
@@ -200,11 +208,69 @@ template <class R> __device__ __forceinline__ int layer_idx(const Tgt<R>& T, dou
     const int dn = (u < elo && l > 0) ? 1 : 0;
     return l + up - dn;
 }
+template <class R> __device__ __forceinline__ int layer_idx(const Tgt<R>& T, double u) {
+    return layer_idx_s(T, u, T.e0, T.inv_h);
+}
 
-template <class R> __device__ __forceinline__ LPt lpt(const Tgt<R>& T, V3<R> p) {
-    if (T.mcnt == 1) return LPt{0.0, 0};
-    const double u = axis_u(T, p);
-    return LPt{u, layer_idx(T, u)};
+// The exact (FP64) axis coordinate and layer of p, with the medium's axis and
+// spacing read from its record (the FP32 step keeps only their FP32 forms).
+template <class R> __device__ __forceinline__ double axis_u_m(const Tgt<R>& T, V3<R> p) {
+    const MedInfo& m = *T.mi;
+    return T.usrc + m.ax * (double)p.x + m.ay * (double)p.y + m.az * (double)p.z;
+}
+
+// Axis position of edge k relative to the source (FP32 lookups).
+template <class R> __device__ __forceinline__ R edge_rel(const Tgt<R>& T, int k) {
+    return T.uniform ? ((R)(k - T.lsrc) - T.fsrc) * Mth<R>::rcp(T.ihr) : (R)(T.edge[k] - T.usrc);
+}
+
+// Fractional layer coordinates closer than this to an integer, or farther
+// than LAYER_REACH layers from the source's, leave the layer to the exact
+// lookup: the FP32 layer coordinate is good to 2.5e-5 layers within 64
+// layers of the source.
+constexpr float LAYER_MARGIN = 0x1p-15f;
+constexpr float LAYER_REACH = 64.0f;
+
+// Layer point of p.  FP64: exact.  FP32: u relative to the source in FP32
+// and the layer from the fractional layer coordinate; `near` reports the
+// points whose layer lpt_settle must decide (near an edge, far from the
+// source, or in a medium with unevenly spaced edges).
+template <class R> __device__ __forceinline__ LPt<R> lpt_fast(const Tgt<R>& T, V3<R> p, bool& near) {
+    near = false;
+    if (T.mcnt == 1) return LPt<R>{(R)0, 0};
+    if constexpr (sizeof(R) == 8) {
+        const double u = axis_u(T, p);
+        return LPt<R>{u, layer_idx(T, u)};
+    } else {
+        const R x = T.axr.x * p.x + T.axr.y * p.y + T.axr.z * p.z;
+        const R xi = T.fsrc + x * T.ihr;
+        const R fl = floorf(xi), fr = xi - fl;
+        const R lf = fminf(fmaxf((R)T.lsrc + fl, (R)0), (R)(T.mcnt - 1));
+        near = !T.uniform || fr < (R)LAYER_MARGIN || fr > (R)1 - (R)LAYER_MARGIN || !(fabsf(xi) < (R)LAYER_REACH);
+        return LPt<R>{x, (int)lf};
+    }
+}
+
+// The exact (FP64) layer of p for an FP32 layer point, with u kept inside
+// the real edges of that layer, so that the depth pieces of a crossing are
+// never negative (no-op in FP64).
+template <class R> __device__ __forceinline__ void lpt_settle(const Tgt<R>& T, V3<R> p, LPt<R>& q) {
+    if constexpr (sizeof(R) == 4) {
+        if (T.mcnt == 1) return;
+        const MedInfo& m = *T.mi;
+        const int l = layer_idx_s(T, axis_u_m(T, p), m.e0, m.inv_h);
+        R x = q.u;
+        if (l >= 1) x = fmaxf(x, edge_rel(T, l));
+        if (l <= T.mcnt - 2) x = fminf(x, edge_rel(T, l + 1));
+        q = LPt<R>{x, l};
+    }
+}
+
+template <class R> __device__ __forceinline__ LPt<R> lpt(const Tgt<R>& T, V3<R> p) {
+    bool near;
+    LPt<R> q = lpt_fast(T, p, near);
+    if (near) lpt_settle(T, p, q);
+    return q;
 }
 
 // Optical depths of the segment P -> Q of length len: total c = a + b and
@@ -244,10 +310,36 @@ __device__ __forceinline__ void seg_depth(const Tgt<R>& T, V3<R> P, V3<R> Q, R l
 
 // seg_depth with the endpoints' layer points already known.
 template <class R>
-__device__ __forceinline__ void seg_depth_lp(const Tgt<R>& T, LPt P, LPt Q, R len, R& tc, R& tb) {
+__device__ __forceinline__ void seg_depth_lp(const Tgt<R>& T, LPt<R> P, LPt<R> Q, R len, R& tc, R& tb) {
     if (T.mcnt == 1) {
         tc = T.l0.c * len;
         tb = T.l0.b * len;
+        return;
+    }
+    if constexpr (sizeof(R) == 4) {
+        // FP32: the partial layers at both ends from the relative coordinates
+        // (each piece as precise as the vertices), the whole layers between
+        // from the FP64 prefix integrals
+        const bool swap = P.u > Q.u;
+        const R lo = swap ? Q.u : P.u, hi = swap ? P.u : Q.u;
+        const int llo = swap ? Q.l : P.l, lhi = swap ? P.l : Q.l;
+        const R* a = T.lay + llo * LY_NW;
+        const R* b = T.lay + lhi * LY_NW;
+        const R ac = a[LY_C], ab = a[LY_B], bc = b[LY_C], bb = b[LY_B];
+        const double2 ph = T.pre[llo + 1], pl = T.pre[lhi];
+        const bool same = P.l == Q.l;
+        // mean coefficient = c_hi + (c_lo - c_hi) f + (I_mid - c_hi W) / (hi - lo),
+        // f = the share of the low layer, W the width of the whole layers
+        // between (0 and I_mid = 0 for neighbouring layers): a thin crossing
+        // errs by at most |c_lo - c_hi| of its length
+        const R d1 = edge_rel(T, llo + 1) - lo;
+        const R W = T.uniform ? (R)(lhi - llo - 1) * Mth<R>::rcp(T.ihr) : (R)(T.edge[lhi] - T.edge[llo + 1]);
+        const R ir = Mth<R>::rcp(same ? (R)1 : fmaxf(hi - lo, (R)0x1p-100));
+        const R f = fminf(d1 * ir, (R)1);
+        const R mc = bc + (ac - bc) * f + ((R)(pl.x - ph.x) - bc * W) * ir;
+        const R mb = bb + (ab - bb) * f + ((R)(pl.y - ph.y) - bb * W) * ir;
+        tc = (same ? ac : mc) * len;
+        tb = (same ? ab : mb) * len;
         return;
     }
     // evaluated for every lane and selected (no divergent branch): inside one
@@ -337,7 +429,8 @@ template <class R> __device__ __forceinline__ Seg<R> make_seg(const Tgt<R>& T, V
     return s;
 }
 
-template <class R> __device__ __forceinline__ Seg<R> make_seg_lp(const Tgt<R>& T, V3<R> P, V3<R> Q, LPt lP, LPt lQ) {
+template <class R>
+__device__ __forceinline__ Seg<R> make_seg_lp(const Tgt<R>& T, V3<R> P, V3<R> Q, LPt<R> lP, LPt<R> lQ) {
     Seg<R> s;
     V3<R> r = Q - P;
     R l2 = dot(r, r);
@@ -419,6 +512,15 @@ __device__ __forceinline__ void load_target(const KArgs& a, int t, Tgt<R>& T, co
     T.e0 = mi.e0;
     T.inv_h = mi.inv_h;
     T.usrc = mi.ax * o[0] + mi.ay * o[1] + mi.az * o[2];
+    T.mi = a.minfo + a.medium[t];
+    T.axr = {(R)mi.ax, (R)mi.ay, (R)mi.az};
+    {
+        const double xs = (T.usrc - mi.e0) * mi.inv_h;
+        const double fl = floor(xs);
+        T.lsrc = (int)fmin(fmax(fl, -1e9), 1e9);
+        T.fsrc = (R)(xs - fl);
+        T.ihr = (R)mi.inv_h;
+    }
     T.lay = tab.lay + (size_t)mi.off * LY_NW;
     T.l0 = lay_load(T.lay);
     int eo = mi.off + a.medium[t];

@@ -95,7 +95,8 @@ template <class R> struct GlobalPath {
 template <class R, class P>
 __device__ __forceinline__ double full_logp(const Tgt<R>& T, const P& ps, int n, double& L, double* Sb = nullptr) {
     V3<R> f0 = ps.p(0), f1 = ps.p(1);
-    Seg<R> s = make_seg(T, f0, f1);
+    LPt<R> lc = lpt(T, f1);
+    Seg<R> s = make_seg_lp(T, f0, f1, lpt(T, f0), lc);
     bool zero = !(s.len > (R)0);
     double lp = (double)emit_term(T, s.u) + (double)seg_term(s);
     L = (double)s.len;
@@ -104,15 +105,17 @@ __device__ __forceinline__ double full_logp(const Tgt<R>& T, const P& ps, int n,
     V3<R> fc = f1;
     for (int k = 1; k <= n - 2; ++k) {
         V3<R> fn = ps.p(k + 1);
-        Seg<R> s2 = make_seg(T, fc, fn);
+        const LPt<R> lnx = lpt(T, fn);
+        Seg<R> s2 = make_seg_lp(T, fc, fn, lc, lnx);
         zero |= !(s2.len > (R)0);
-        const LayV<R> ly = lay_of(T, fc);
+        const LayV<R> ly = lay_at(T, lc.l);
         lp += (double)(ly.logb + turn_term(ly, s.u, s2.u)) + (double)seg_term(s2);
         L += (double)s2.len;
         sb += (double)s2.tb;
         ps.stw(k, s2.tb);
         s = s2;
         fc = fn;
+        lc = lnx;
     }
     lp += (double)end_term(T, s.u, fc);
     if (zero) lp = -__builtin_inf();
@@ -170,40 +173,22 @@ __device__ __forceinline__ void box_muller3(uint32_t a, uint32_t b, uint32_t c, 
 // with a three-vertex register window.  emit(k, g) receives the finished
 // gradient of vertex k (k = 0 .. n-1, in increasing order).
 // ---------------------------------------------------------------------------
+// d tau_c / d P and d tau_c / d Q of a segment with the endpoints' layer
+// points known: the mean coefficient along the segment, plus the change of
+// the layers' shares where it crosses edges.
 template <class R>
-__device__ __forceinline__ void seg_depth_grad(const Tgt<R>& T, V3<R> P, V3<R> Q, const Seg<R>& s, V3<R>& dP,
-                                               V3<R>& dQ) {
-    R F = s.tc * Mth<R>::rcp(s.len); // mean total coefficient along the segment
-    dP = (-F) * s.u;
-    dQ = F * s.u;
-    if (T.mcnt > 1) {
-        double uP = axis_u(T, P), uQ = axis_u(T, Q);
-        int lP = layer_u(T, uP), lQ = layer_u(T, uQ);
-        if (lP != lQ) {
-            double cP = (double)T.lay[lP * LY_NW + LY_C], cQ = (double)T.lay[lQ * LY_NW + LY_C];
-            double inv = 1.0 / (uQ - uP);
-            R gP = (R)((double)s.len * ((double)F - cP) * inv);
-            R gQ = (R)((double)s.len * (cQ - (double)F) * inv);
-            V3<R> ax = {(R)T.ax, (R)T.ay, (R)T.az};
-            dP = dP + gP * ax;
-            dQ = dQ + gQ * ax;
-        }
-    }
-}
-
-// seg_depth_grad with the endpoints' layer points already known.
-template <class R>
-__device__ __forceinline__ void seg_depth_grad_lp(const Tgt<R>& T, LPt P, LPt Q, const Seg<R>& s, V3<R>& dP,
+__device__ __forceinline__ void seg_depth_grad_lp(const Tgt<R>& T, LPt<R> P, LPt<R> Q, const Seg<R>& s, V3<R>& dP,
                                                   V3<R>& dQ) {
     R F = s.tc * Mth<R>::rcp(s.len); // mean total coefficient along the segment
     dP = (-F) * s.u;
     dQ = F * s.u;
     if (T.mcnt > 1 && P.l != Q.l) {
         double cP = (double)T.lay[P.l * LY_NW + LY_C], cQ = (double)T.lay[Q.l * LY_NW + LY_C];
-        double inv = 1.0 / (Q.u - P.u);
+        const double du = (double)Q.u - (double)P.u;
+        const double inv = du != 0.0 ? 1.0 / du : 0.0;
         R gP = (R)((double)s.len * ((double)F - cP) * inv);
         R gQ = (R)((double)s.len * (cQ - (double)F) * inv);
-        V3<R> ax = {(R)T.ax, (R)T.ay, (R)T.az};
+        const V3<R> ax = T.axr;
         dP = dP + gP * ax;
         dQ = dQ + gQ * ax;
     }
@@ -240,8 +225,8 @@ enum { VK_EMIT = 0, VK_TURN = 1, VK_END = 2, VK_NONE = 3 };
 // log(-u . nu) when f_{j+1} is the end point).  log b(f_j) is constant within
 // a layer and contributes nothing.
 template <class R>
-__device__ __forceinline__ V3<R> vertex_grad(const Tgt<R>& T, int km1, const LayV<R>& lm1, V3<R> um, LPt pm1,
-                                             LPt po, LPt pp1, const Seg<R>& A, const Seg<R>& B,
+__device__ __forceinline__ V3<R> vertex_grad(const Tgt<R>& T, int km1, const LayV<R>& lm1, V3<R> um, LPt<R> pm1,
+                                             LPt<R> po, LPt<R> pp1, const Seg<R>& A, const Seg<R>& B,
                                              const LayV<R>& lo, int kp1, V3<R> up, V3<R> nu1, const LayV<R>& lp1) {
     V3<R> dPA, dQA, dPB, dQB;
     seg_depth_grad_lp(T, pm1, po, A, dPA, dQA);
@@ -284,7 +269,7 @@ template <class R> struct ScoreWalker {
     bool zero;
     int k; // next vertex to consume
 
-    __device__ __forceinline__ void init(V3<R> f0) {
+    __device__ __forceinline__ void init(const Tgt<R>& T, V3<R> f0) {
         const V3<R> z = {(R)0, (R)0, (R)0};
         gA = z;
         gB = z;
@@ -297,11 +282,14 @@ template <class R> struct ScoreWalker {
     }
 
     __device__ __forceinline__ bool step(const Tgt<R>& T, V3<R> fcur, V3<R>& gout) {
-        Seg<R> s = make_seg(T, fprev, fcur);
+        // (the layer point of fprev is looked up again rather than kept: two
+        // walks advance together and their registers are scarce)
+        const LPt<R> pprev = lpt(T, fprev), pcur = lpt(T, fcur);
+        Seg<R> s = make_seg_lp(T, fprev, fcur, pprev, pcur);
         zero |= !(s.len > (R)0);
         lp += (double)seg_term(s);
         V3<R> dP, dQ;
-        seg_depth_grad(T, fprev, fcur, s, dP, dQ);
+        seg_depth_grad_lp(T, pprev, pcur, s, dP, dQ);
         R il2 = (R)2 * Mth<R>::rcp(s.len);
         gB = gB - dP + il2 * s.u;
         const V3<R> z = {(R)0, (R)0, (R)0};
@@ -315,7 +303,7 @@ template <class R> struct ScoreWalker {
             }
         } else {
             // turn (and scattering density) at vertex k-1 between sprev and s
-            const LayV<R> ly = lay_of(T, fprev);
+            const LayV<R> ly = lay_at(T, pprev.l);
             V3<R> dd = uprev - s.u;
             lp += (double)(ly.logb + turn_term(ly, uprev, s.u));
             R h = dturn_dmu(ly, dot(dd, dd));
@@ -363,7 +351,7 @@ template <class R> struct ScoreWalker {
 template <class R, class P, class Emit>
 __device__ __forceinline__ double score_stream(const Tgt<R>& T, const P& ps, int n, Emit emit) {
     ScoreWalker<R> w;
-    w.init(ps.p(0));
+    w.init(T, ps.p(0));
     V3<R> g, g2;
     for (int k = 1; k < n; ++k)
         if (w.step(T, ps.p(k), g)) emit(k - 2, g);
@@ -707,8 +695,8 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
             double half_xi2 = 0.0, rev = 0.0;
             ScoreWalker<R> wx, wy;
             const V3<R> x0 = ps.p(0);
-            wx.init(x0);
-            wy.init(x0);
+            wx.init(T, x0);
+            wy.init(T, x0);
             // y_k, y_{k-1}, y_{k-2} of the last vertex k fed to the y walk, kept
             // as scalars so that the ring stays in registers
             R y0x = x0.x, y0y = x0.y, y0z = x0.z, y1x = x0.x, y1y = x0.y, y1z = x0.z;
@@ -779,11 +767,30 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
         const V3<R> fp1 = hp1 ? gp1 : fo + ex;
         const V3<R> fp2 = hp2 ? gp2 : fp1 + ex;
         move = is_end ? MV_END : MV_INTERIOR;
-        // layer points of the window vertices, once each
-        const LPt pm1 = lpt(T, fm1), po = lpt(T, fo), pp1 = lpt(T, fp1);
-        const Seg<R> Ao = make_seg_lp(T, fm1, fo, pm1, po), Bo = make_seg_lp(T, fo, fp1, po, pp1);
+        // layer points of the window vertices, once each; the ones near an
+        // edge are settled together with the proposal's (one branch per
+        // step), except that the Langevin step needs the old window first
+        constexpr bool EARLY = SAMP == SAMP_LOCAL;
+        bool q1, q2, q3, q4;
+        LPt<R> pm1 = lpt_fast(T, fm1, q1), po = lpt_fast(T, fo, q2), pp1 = lpt_fast(T, fp1, q3);
+        if constexpr (EARLY) {
+            if (q1 | q2 | q3) {
+                lpt_settle(T, fm1, pm1);
+                lpt_settle(T, fo, po);
+                lpt_settle(T, fp1, pp1);
+            }
+        }
+        Seg<R> Ao, Bo;
+        LayV<R> lm1, lo, lp1;
+        auto old_window = [&]() __attribute__((always_inline)) {
+            Ao = make_seg_lp(T, fm1, fo, pm1, po);
+            Bo = make_seg_lp(T, fo, fp1, po, pp1);
+            lm1 = lay_at(T, pm1.l);
+            lo = lay_at(T, po.l);
+            lp1 = lay_at(T, pp1.l);
+        };
+        if constexpr (EARLY) old_window();
         const V3<R> um = unit_dir(fm2, fm1), up = unit_dir(fp1, fp2), nu1 = unit_dir_eta(T, fp1);
-        const LayV<R> lm1 = lay_at(T, pm1.l), lo = lay_at(T, po.l), lp1 = lay_at(T, pp1.l);
         const int km1 = hm2 ? VK_TURN : VK_EMIT;
         const int kj = is_end ? VK_END : VK_TURN;
         const int kp1 = !hp1 ? VK_NONE : (hp2 ? VK_TURN : VK_END);
@@ -819,7 +826,18 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
             nn = wv * nu + sw * (c5 * e2 + s5 * e3); // sensor normal at the proposed end point
             fn = is_end ? T.eta + (T.eta_lo + T.rad * nn) : fg;
         }
-        const LPt pn = lpt(T, fn);
+        LPt<R> pn = lpt_fast(T, fn, q4);
+        if constexpr (EARLY) {
+            if (q4) lpt_settle(T, fn, pn);
+        } else {
+            if (q1 | q2 | q3 | q4) {
+                lpt_settle(T, fm1, pm1);
+                lpt_settle(T, fo, po);
+                lpt_settle(T, fp1, pp1);
+                lpt_settle(T, fn, pn);
+            }
+            old_window();
+        }
         const Seg<R> An = make_seg_lp(T, fm1, fn, pm1, pn), Bn = make_seg_lp(T, fn, fp1, pn, pp1);
         const LayV<R> lnw = lay_at(T, pn.l);
         R d = seg_term(An) - seg_term(Ao);
@@ -930,10 +948,16 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
     }
     const V3<R> fprev = hprev ? gprev : A - ex;
     const V3<R> fnext = hnext ? gnext : B + ex;
-    const LPt pA = lpt(T, A), pB = lpt(T, B);
-    const Seg<R> AB = make_seg_lp(T, A, B, pA, pB);
     const V3<R> mid = (R)0.5 * (A + B);
-    const LayV<R> lm = lay_of(T, mid);
+    bool q1, q2, q3;
+    LPt<R> pA = lpt_fast(T, A, q1), pB = lpt_fast(T, B, q2), pmid = lpt_fast(T, mid, q3);
+    if (q1 | q2 | q3) {
+        lpt_settle(T, A, pA);
+        lpt_settle(T, B, pB);
+        lpt_settle(T, mid, pmid);
+    }
+    const Seg<R> AB = make_seg_lp(T, A, B, pA, pB);
+    const LayV<R> lm = lay_at(T, pmid.l);
     const R gam = (R)0.5 * AB.len;
     const R beta = lm.keq + (R)0.5 * (gam * lm.b - (R)1); // centering rule at the midpoint
     const QS<R> qs = make_qs(beta);
@@ -952,7 +976,7 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
         const V3<R> fb = mid + sc_ * ((a5 - b5) * AB.u + (ab2 * ss) * tr);
         fv = birth ? fb : fj;
     }
-    const LPt pv = lpt(T, fv);
+    const LPt<R> pv = lpt(T, fv);
     const Seg<R> sA = make_seg_lp(T, A, fv, pA, pv), sB = make_seg_lp(T, fv, B, pv, pB);
     const V3<R> up = unit_dir(fprev, A), un = unit_dir(B, fnext), nuB = unit_dir_eta(T, B);
     const LayV<R> la = lay_at(T, pA.l), lb = lay_at(T, pB.l), lv = lay_at(T, pv.l);
