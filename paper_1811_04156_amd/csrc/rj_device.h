@@ -119,9 +119,9 @@ template <class R> struct Tgt {
     bool sl;      // false: no layer of the medium mixes in the Rayleigh-like term
     double ax, ay, az, e0, inv_h, usrc;
     // the FP32 layer lookups: the axis rounded, the source's position in layer
-    // units split into its layer lsrc and the fraction fsrc, and 1 / h
+    // units split into its layer lsrc and the fraction fsrc, 1 / h and h
     V3<R> axr;
-    R fsrc, ihr;
+    R fsrc, ihr, hr;
     int lsrc;
     const MedInfo* mi;   // the medium's axis and spacing (the exact lookups read them here)
     LayV<R> l0;          // layer 0 (the only one of a homogeneous medium)
@@ -221,7 +221,7 @@ template <class R> __device__ __forceinline__ double axis_u_m(const Tgt<R>& T, V
 
 // Axis position of edge k relative to the source (FP32 lookups).
 template <class R> __device__ __forceinline__ R edge_rel(const Tgt<R>& T, int k) {
-    return T.uniform ? ((R)(k - T.lsrc) - T.fsrc) * Mth<R>::rcp(T.ihr) : (R)(T.edge[k] - T.usrc);
+    return T.uniform ? ((R)(k - T.lsrc) - T.fsrc) * T.hr : (R)(T.edge[k] - T.usrc);
 }
 
 // Fractional layer coordinates closer than this to an integer, or farther
@@ -333,7 +333,7 @@ __device__ __forceinline__ void seg_depth_lp(const Tgt<R>& T, LPt<R> P, LPt<R> Q
         // between (0 and I_mid = 0 for neighbouring layers): a thin crossing
         // errs by at most |c_lo - c_hi| of its length
         const R d1 = edge_rel(T, llo + 1) - lo;
-        const R W = T.uniform ? (R)(lhi - llo - 1) * Mth<R>::rcp(T.ihr) : (R)(T.edge[lhi] - T.edge[llo + 1]);
+        const R W = T.uniform ? (R)(lhi - llo - 1) * T.hr : (R)(T.edge[lhi] - T.edge[llo + 1]);
         const R ir = Mth<R>::rcp(same ? (R)1 : fmaxf(hi - lo, (R)0x1p-100));
         const R f = fminf(d1 * ir, (R)1);
         const R mc = bc + (ac - bc) * f + ((R)(pl.x - ph.x) - bc * W) * ir;
@@ -520,6 +520,7 @@ __device__ __forceinline__ void load_target(const KArgs& a, int t, Tgt<R>& T, co
         T.lsrc = (int)fmin(fmax(fl, -1e9), 1e9);
         T.fsrc = (R)(xs - fl);
         T.ihr = (R)mi.inv_h;
+        T.hr = (R)(1.0 / mi.inv_h);
     }
     T.lay = tab.lay + (size_t)mi.off * LY_NW;
     T.l0 = lay_load(T.lay);

@@ -75,6 +75,63 @@ def test_logp_and_gradient_parity(rj, prec, nmax, cap):
     print(f"{prec} nmax={nmax}: worst per-vertex gradient error {worst:.2e}")
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_layer_lookups_near_edges(rj, prec):
+    """The step kernel's layer lookups on paths whose vertices sit on layer
+    edges or a few FP32 ulps to either side, and whose segments cross an edge
+    almost parallel to it (FP32: coordinates relative to the source, the
+    layer settled in FP64 within 2^-15 layers of an edge).  A one-step launch
+    whose moves change nothing but rounding refreshes log p at its end; it
+    agrees with the oracle's log p of the read-back paths within the a-priori
+    FP32 bound (FP64: 1e-9), and the FP32 settle was exercised."""
+    from gpu_helpers import BASE_BOUND, EPS32, K_BOUND
+    w = mixed_workload(cap=48, chains=256)
+    O, orc = _oracle(w)
+    rng = np.random.default_rng(11)
+    n, V = random_paths(orc, w, rng, 24)
+    edges = np.asarray(w["edges"], np.float64)
+    h = edges[1] - edges[0]
+    tgt = np.asarray(w["c_target"])
+    src = np.asarray(w["t_src"])
+    for c in range(len(n)):
+        t = int(tgt[c])
+        zs = src[t, 2]
+        x = V[c].copy()
+        for k in range(2, n[c] - 2):
+            mode = int(rng.integers(0, 3))
+            e = edges[np.argmin(np.abs(edges - (x[k, 2] + zs)))]
+            if mode == 1:  # on the edge or a few ulps off it
+                x[k, 2] = (e - zs) + rng.choice([0.0, 1e-7, -1e-7, 2e-6, -2e-6, 3e-5, -3e-5])
+            elif mode == 2 and k + 1 < n[c] - 2:  # a segment crossing the edge almost parallel to it
+                d = rng.choice([1e-6, 1e-5, 1e-3])
+                x[k, 2], x[k + 1, 2] = (e - zs) - d, (e - zs) + d
+        if np.isfinite(orc.logp(t, x[: n[c]])):
+            V[c] = x
+    s = rj.Sampler(w, precision=prec)
+    s.set_state(n, V)
+    s.run(1, run=dict(cycle_len=1, n_perturb=1, sigma=1e-30, kappa_end=1e30))
+    torch.cuda.synchronize()
+    lp = s.logp.cpu().numpy()
+    n2, V2 = s.get_state()
+    worst, near = 0.0, 0
+    for c in range(len(n2)):
+        t = int(tgt[c])
+        x = V2[c, : n2[c]]
+        ref = orc.logp(t, x)
+        xi = (x[:, 2] + src[t, 2] - edges[0]) / h
+        fr = xi - np.floor(xi)
+        near += int(np.sum((np.minimum(fr, 1 - fr) < 2.0 ** -15) & (xi > 0.5) & (xi < len(edges) - 1.5)))
+        if prec == "f64":
+            assert abs(lp[c] - ref) < 1e-9, (c, lp[c], ref)
+            continue
+        g = orc.grad(t, x, params=False)
+        bound = BASE_BOUND + K_BOUND * EPS32 * float(np.sum(np.abs(g).sum(1) * (np.abs(x).sum(1) + 1.0)))
+        worst = max(worst, abs(lp[c] - ref) / bound)
+    print(f"{prec}: {near} vertices within 2^-15 layers of an edge, worst |log p - oracle| / bound {worst:.3f}")
+    assert near >= 100
+    assert worst <= 1.0
+
+
 @pytest.mark.parametrize("birth_frac", [0.5, 0.3])
 def test_fp64_free_run_matches_oracle(rj, birth_frac):
     """The reference single target (FP64): the device run and the oracle take the same decisions
