@@ -202,6 +202,8 @@ def proposal_candidates(w, sampler):
     for sig in (0.5, 1.0, 2.0, 4.0):
         for npert in (2, 3):
             out.append(dict(base, sigma=sig, cycle_len=5, n_perturb=npert))
+    for sig in (1.0, 2.0):
+        out.append(dict(base, sigma=sig, cycle_len=5, n_perturb=4))
     for kap in (5.0, 60.0):
         out.append(dict(base, kappa_end=kap))
     if sampler == "langevin":
