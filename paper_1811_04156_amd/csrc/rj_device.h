@@ -176,13 +176,6 @@ template <class R> __device__ __forceinline__ int layer_at(const Tgt<R>& T, V3<R
     return layer_u(T, axis_u(T, p));
 }
 
-template <class R> __device__ __forceinline__ LayV<R> lay_of(const Tgt<R>& T, V3<R> p) {
-    if (T.mcnt == 1) return T.l0;
-    LayV<R> ly = lay_load(T.lay + layer_u(T, axis_u(T, p)) * LY_NW);
-    if (!T.sl) ly.fsl = (R)0;
-    return ly;
-}
-
 // A point's coordinate along the layer axis and its layer index, computed
 // once per vertex and step and shared by every factor and segment that
 // touches the vertex.  FP64: the absolute coordinate; FP32: the coordinate
