@@ -79,6 +79,70 @@ template <class R, bool LO> struct PathRef {
         if (LO || v < V) ((LdsScalar<R>)(lds + v * WAVE))[3] = x;
         else glb[(size_t)v * C].w = x;
     }
+    // The vertex shifts of an accepted jump, split at the LDS/HBM boundary
+    // into loops that touch one memory each (no per-vertex branch on the
+    // address space), each reading four vertices before writing them (one
+    // latency per four): slots lo..hi move one slot up (from the top) ...
+    __device__ __forceinline__ void lds_up(int& v, int lo) const {
+        for (; v - 3 >= lo; v -= 4) {
+            const L4<R> a = lds[v * WAVE], b = lds[(v - 1) * WAVE], c = lds[(v - 2) * WAVE], d = lds[(v - 3) * WAVE];
+            lds[(v + 1) * WAVE] = a;
+            lds[v * WAVE] = b;
+            lds[(v - 1) * WAVE] = c;
+            lds[(v - 2) * WAVE] = d;
+        }
+        for (; v >= lo; --v) lds[(v + 1) * WAVE] = lds[v * WAVE];
+    }
+    __device__ __forceinline__ void shift_up(int lo, int hi) const {
+        int v = hi;
+        if (!LO) {
+            L4<R>* const g = (L4<R>*)glb;
+            for (; v - 3 >= lo && v - 3 >= V; v -= 4) {
+                const L4<R> a = g[(size_t)v * C], b = g[(size_t)(v - 1) * C], c = g[(size_t)(v - 2) * C],
+                            d = g[(size_t)(v - 3) * C];
+                g[(size_t)(v + 1) * C] = a;
+                g[(size_t)v * C] = b;
+                g[(size_t)(v - 1) * C] = c;
+                g[(size_t)(v - 2) * C] = d;
+            }
+            for (; v >= lo && v >= V; --v) g[(size_t)(v + 1) * C] = g[(size_t)v * C];
+            if (v >= lo && v == V - 1) {
+                g[(size_t)V * C] = lds[v * WAVE];
+                --v;
+            }
+        }
+        lds_up(v, lo);
+    }
+    // ... or slots lo+1..hi+1 move one slot down (from the bottom).
+    __device__ __forceinline__ void shift_down(int lo, int hi) const {
+        int v = lo;
+        const int top = LO ? hi : (hi < V - 2 ? hi : V - 2); // the moves that stay in LDS
+        for (; v + 3 <= top; v += 4) {
+            const L4<R> a = lds[(v + 1) * WAVE], b = lds[(v + 2) * WAVE], c = lds[(v + 3) * WAVE],
+                        d = lds[(v + 4) * WAVE];
+            lds[v * WAVE] = a;
+            lds[(v + 1) * WAVE] = b;
+            lds[(v + 2) * WAVE] = c;
+            lds[(v + 3) * WAVE] = d;
+        }
+        for (; v <= top; ++v) lds[v * WAVE] = lds[(v + 1) * WAVE];
+        if (!LO) {
+            L4<R>* const g = (L4<R>*)glb;
+            if (v <= hi && v == V - 1) {
+                lds[v * WAVE] = g[(size_t)V * C];
+                ++v;
+            }
+            for (; v + 3 <= hi; v += 4) {
+                const L4<R> a = g[(size_t)(v + 1) * C], b = g[(size_t)(v + 2) * C], c = g[(size_t)(v + 3) * C],
+                            d = g[(size_t)(v + 4) * C];
+                g[(size_t)v * C] = a;
+                g[(size_t)(v + 1) * C] = b;
+                g[(size_t)(v + 2) * C] = c;
+                g[(size_t)(v + 3) * C] = d;
+            }
+            for (; v <= hi; ++v) g[(size_t)v * C] = g[(size_t)(v + 1) * C];
+        }
+    }
 };
 
 template <class R> struct GlobalPath {
@@ -1018,7 +1082,7 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
         fold_hist(ln, sc);
         const double dL = (double)sA.len + (double)sB.len - (double)AB.len;
         if (birth) {
-            for (int v = n - 1; v >= iB; --v) ps.st(v + 1, ps.ld(v));
+            ps.shift_up(iB, n - 1);
             ps.st(iB, Vtx<R>{fv.x, fv.y, fv.z, sB.tb});
             ps.stw(iA, sA.tb);
             ln.L += dL;
@@ -1030,7 +1094,7 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
                 ln.lwp = sc.logw[n + 2 <= sc.cap ? n + 2 : sc.cap];
             }
         } else {
-            for (int v = jv; v <= n - 2; ++v) ps.st(v, ps.ld(v + 1));
+            ps.shift_down(jv, n - 2);
             ps.stw(iA, AB.tb);
             ln.L -= dL;
             ln.S = Sx;
