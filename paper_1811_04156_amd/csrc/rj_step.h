@@ -79,6 +79,32 @@ template <class R, bool LO> struct PathRef {
         if (LO || v < V) ((LdsScalar<R>)(lds + v * WAVE))[3] = x;
         else glb[(size_t)v * C].w = x;
     }
+    // Five vertices at once.  LDS-only: five reads.  Otherwise five LDS
+    // reads (the indices that lie in HBM read the padding slot V instead)
+    // and, for the lanes whose five reach HBM, one branch that reads all five
+    // from HBM and keeps those (no branch per vertex on the address space).
+    __device__ __forceinline__ void ld5(int i0, int i1, int i2, int i3, int i4, Vtx<R>& o0, Vtx<R>& o1, Vtx<R>& o2,
+                                        Vtx<R>& o3, Vtx<R>& o4) const {
+        const int c0 = LO || i0 < V ? i0 : V, c1 = LO || i1 < V ? i1 : V, c2 = LO || i2 < V ? i2 : V;
+        const int c3 = LO || i3 < V ? i3 : V, c4 = LO || i4 < V ? i4 : V;
+        o0 = lds_ld<R>(lds + c0 * WAVE);
+        o1 = lds_ld<R>(lds + c1 * WAVE);
+        o2 = lds_ld<R>(lds + c2 * WAVE);
+        o3 = lds_ld<R>(lds + c3 * WAVE);
+        o4 = lds_ld<R>(lds + c4 * WAVE);
+        if (LO) return;
+        const int hi = max(max(max(i0, i1), max(i2, i3)), i4);
+        if (hi >= V) {
+            const L4<R>* const g = (const L4<R>*)glb;
+            const L4<R> g0 = g[(size_t)i0 * C], g1 = g[(size_t)i1 * C], g2 = g[(size_t)i2 * C];
+            const L4<R> g3 = g[(size_t)i3 * C], g4 = g[(size_t)i4 * C];
+            if (i0 >= V) o0 = Vtx<R>{g0.x, g0.y, g0.z, g0.w};
+            if (i1 >= V) o1 = Vtx<R>{g1.x, g1.y, g1.z, g1.w};
+            if (i2 >= V) o2 = Vtx<R>{g2.x, g2.y, g2.z, g2.w};
+            if (i3 >= V) o3 = Vtx<R>{g3.x, g3.y, g3.z, g3.w};
+            if (i4 >= V) o4 = Vtx<R>{g4.x, g4.y, g4.z, g4.w};
+        }
+    }
     // The vertex shifts of an accepted jump, split at the LDS/HBM boundary
     // into loops that touch one memory each (no per-vertex branch on the
     // address space), each reading four vertices before writing them (one
@@ -832,9 +858,10 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
         // slots j-2 .. j+2 (absent neighbours are replaced by stand-ins below;
         // in LDS their slots are readable as they are, elsewhere the indices
         // are clamped to stay in range)
-        const Vtx<R> vm1 = ps.ld(j - 1), vo = ps.ld(j);
-        const V3<R> gm2 = ps.p(LO || hm2 ? j - 2 : 0), fm1 = pos(vm1), fo = pos(vo);
-        const V3<R> gp1 = ps.p(LO || hp1 ? j + 1 : 0), gp2 = ps.p(LO || hp2 ? j + 2 : 0);
+        Vtx<R> wm2, vm1, vo, wp1, wp2;
+        ps.ld5(LO || hm2 ? j - 2 : 0, j - 1, j, LO || hp1 ? j + 1 : 0, LO || hp2 ? j + 2 : 0, wm2, vm1, vo, wp1, wp2);
+        const V3<R> gm2 = pos(wm2), fm1 = pos(vm1), fo = pos(vo);
+        const V3<R> gp1 = pos(wp1), gp2 = pos(wp2);
         const V3<R> fm2 = hm2 ? gm2 : fm1 - ex;
         const V3<R> fp1 = hp1 ? gp1 : fo + ex;
         const V3<R> fp2 = hp2 ? gp2 : fp1 + ex;
@@ -1009,12 +1036,13 @@ __device__ __forceinline__ void step_body(const Tgt<R>& T, const PathRef<R, LO>&
         B = birth ? pos(s2) : s3;
         gnext = birth ? s3 : s4;
     } else {
-        const Vtx<R> vA = ps.ld(iA), vj = ps.ld(jv);
+        Vtx<R> vA, vj, vB, vp, vn;
+        ps.ld5(iA, jv, iB < n ? iB : n - 1, hprev ? iA - 1 : 0, hnext ? iB + 1 : 0, vA, vj, vB, vp, vn);
         A = pos(vA);
         wA = vA.w;
-        B = ps.p(iB < n ? iB : n - 1);
-        gprev = ps.p(hprev ? iA - 1 : 0);
-        gnext = ps.p(hnext ? iB + 1 : 0);
+        B = pos(vB);
+        gprev = pos(vp);
+        gnext = pos(vn);
         fj = pos(vj);
         wj = vj.w;
     }
