@@ -111,7 +111,7 @@ def parse():
                          "5: perturbations only; skips the proposal tuner)")
     ap.add_argument("--lmala-h", type=float, default=0.05,
                     help="step-size scale of the single-vertex Langevin sampler in the grad-vs-plain leg")
-    ap.add_argument("--proposal-trial", type=int, default=500,
+    ap.add_argument("--proposal-trial", type=int, default=3000,
                     help="sampler steps per candidate and pass of the proposal tuner")
     ap.add_argument("--ess-max-steps", type=int, default=200,
                     help="further benchmark steps allowed after the timed ones to reach 1%% error (ESS/s)")
@@ -353,13 +353,14 @@ def _until_1pct(s, run, chunk, max_steps):
     return done, time.perf_counter() - t0, r
 
 
-def grad_vs_plain(h, max_steps, tree_h=0.3):
+def grad_vs_plain(h, max_steps, tree_h=0.3, trial=3000):
     """262,144 chains on the layered batch's medium and cone-source geometry:
     the plain sampler vs the single-vertex Langevin (gradient-informed)
     sampler and the tree-coordinate sampler (a whole-path move on the first
-    step of every cycle), each after the same sector-tilt tuning and 3000
-    burn-in steps, run until the median target's relative error reaches 1%.
-    ESS/s := 1 / (r^2 t) at that point."""
+    step of every cycle), each after the same sector-tilt tuning, 3000
+    burn-in steps and the proposal tuner over its own candidates (as the
+    headline leg's), run until the median target's relative error reaches
+    1%.  ESS/s := 1 / (r^2 t) at that point."""
     from paper_1811_04156_amd import workloads as W
     from paper_1811_04156_amd.rjpath import LMALA, PLAIN, TREE, Sampler
     out = {}
@@ -370,15 +371,17 @@ def grad_vs_plain(h, max_steps, tree_h=0.3):
         s.tune_tilt(rounds=3, steps=300)
         run = dict(sampler=samp, mala_h=hh, burn_in=0)
         s.run(3000, run=run)
+        cands = proposal_candidates(dict(w, mala_h=hh), name)
+        best, _ = s.tune_proposal(cands, trial, run=run)
+        run.update(cands[best])
         steps, sec, r = _until_1pct(s, run, 4000, max_steps)
         progress(f"grad-vs-plain: {name} sampler, {steps} steps, {sec:.1f} s, r = {r:.4f}")
         st = s.stats.cpu().numpy()
         out[name] = {"steps": steps, "seconds": sec, "median_rel_err": r, "reached_1pct": r <= 0.01,
+                     "proposal": {k: cands[best][k] for k in ("sigma", "kappa_end", "cycle_len", "n_perturb", "mala_h")},
                      "ess_per_s": 1.0 / (r * r * sec), "evals_per_s": evaluated(st) / sec,
                      "perturb_acceptance": float(st[:, 9].sum() / max(1.0, st[:, 6].sum())),
                      "mean_vertices": float(st[:, 5].sum() / max(1.0, st[:, 0].sum()))}
-    out["langevin"]["mala_h"] = h
-    out["tree"]["mala_h"] = tree_h
     out["ess_ratio_langevin_over_plain"] = out["langevin"]["ess_per_s"] / out["plain"]["ess_per_s"]
     out["ess_ratio_tree_over_plain"] = out["tree"]["ess_per_s"] / out["plain"]["ess_per_s"]
     return out
@@ -478,7 +481,8 @@ def main():
     if not args.no_extras:
         out["homogeneous_batch"] = homogeneous_batch(max_steps=args.hom_max_steps)
         progress("homogeneous batch done")
-        out["grad_vs_plain"] = grad_vs_plain(args.lmala_h, args.gvp_max_steps, tree_h=args.tree_h)
+        out["grad_vs_plain"] = grad_vs_plain(args.lmala_h, args.gvp_max_steps, tree_h=args.tree_h,
+                                             trial=args.proposal_trial)
         progress("grad-vs-plain leg done")
     if args.occupancy_probe:
         out["occupancy_probe"] = occupancy_probe()
