@@ -207,7 +207,7 @@ def proposal_candidates(w, sampler):
     for kap in (5.0, 60.0):
         out.append(dict(base, kappa_end=kap))
     if sampler == "langevin":
-        for h in (0.02, 0.1, 0.2):
+        for h in (0.02, 0.1, 0.2, 0.5, 1.0):
             out.append(dict(base, mala_h=h))
     if sampler == "tree":
         for h in (0.1, 1.0):
