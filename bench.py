@@ -188,7 +188,8 @@ def cpu_baseline(w, budget_s):
 
 
 def median_r(I, se):
-    r = se / I
+    with np.errstate(divide="ignore", invalid="ignore"):  # targets without an estimate drop out below
+        r = se / I
     ok = np.isfinite(r) & (r > 0)
     return float(np.median(r[ok])) if ok.any() else float("nan"), int(ok.sum())
 
