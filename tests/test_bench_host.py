@@ -51,8 +51,13 @@ def test_proposal_candidates():
     assert plain[0] == w  # the workload's own proposal first
     assert {c["n_perturb"] for c in plain} == {2, 3, 4}
     assert all(0 < c["n_perturb"] < c["cycle_len"] for c in plain)  # every mix keeps both move classes
+    assert len({tuple(sorted(c.items())) for c in plain}) == len(plain)  # no candidate twice
     lang = bench.proposal_candidates(w, "langevin")
     assert {c["mala_h"] for c in lang} >= {0.02, 0.05, 0.1, 0.2, 0.5, 1.0}
+    # sigma does not enter the Langevin step: its grid is step size x mix
+    assert {c["sigma"] for c in lang} == {1.0}
+    assert {(c["mala_h"], c["n_perturb"]) for c in lang} >= {(h, k) for h in (0.02, 1.0) for k in (2, 3, 4)}
+    assert len({tuple(sorted(c.items())) for c in lang}) == len(lang)
     tree = bench.proposal_candidates(dict(w, mala_h=0.3), "tree")
     assert {c["mala_h"] for c in tree} >= {0.1, 0.3, 1.0}
 
@@ -75,3 +80,32 @@ def test_more_than_one_gpu_is_refused():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr and r.stdout == ""
+
+
+class _FakeTuner:
+    """Stands in for a Sampler: scores are fixed per candidate and trial length."""
+
+    def __init__(self, short, long):
+        self.short, self.long, self.calls = short, long, []
+
+    def tune_proposal(self, cands, trial, run=None):
+        self.calls.append((len(cands), trial))
+        tab = self.short if trial == 100 else self.long
+        sc = np.array([tab[c["id"]] for c in cands])
+        return int(np.argmax(sc)), sc
+
+
+def test_two_stage_tuner_takes_the_best_finalist_of_the_longer_trials():
+    cands = [{"id": i} for i in range(6)]
+    # the short trials rank 4 > 1 > 2; the longer ones put 2 first
+    short = [1.0, 5.0, 4.0, 0.5, 6.0, 3.0]
+    long = [9.0, 2.0, 3.0, 9.0, 1.0, 9.0]
+    f = _FakeTuner(short, long)
+    best, sc1, fin = bench.tune_two_stage(f, cands, 100)
+    assert fin == [4, 1, 2] and best == 2
+    assert f.calls == [(6, 100), (3, 400)]
+    assert list(sc1) == short
+    # fewer candidates than finalists: all of them go through
+    f = _FakeTuner(short, long)
+    best, _, fin = bench.tune_two_stage(f, cands[:2], 100)
+    assert sorted(fin) == [0, 1] and best == 0
