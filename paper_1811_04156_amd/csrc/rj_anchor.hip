@@ -99,7 +99,6 @@ __global__ void __launch_bounds__(256) anchor_kernel(KArgs a, const double* gx, 
     // Gauss-Legendre tables on [0,1]: rule k of size m_k at offset o_k
     // (sizes 8, 16, 32, 64 stored back to back)
     const double* x8 = gx;       const double* w8 = gw;
-    const double* x16 = gx + 8;  const double* w16 = gw + 8;
     const double* x32 = gx + 24; const double* w32 = gw + 24;
     const double* x64 = gx + 56; const double* w64 = gw + 56;
     (void)ngl;
@@ -127,9 +126,14 @@ __global__ void __launch_bounds__(256) anchor_kernel(KArgs a, const double* gx, 
         }
     } else {
         // outer: 32 (inverse-CDF polar) x 32 (azimuth) directions; along each
-        // ray, one 16-point Gauss rule per layer crossed (b jumps and tau kinks
+        // ray, one 32-point Gauss rule per layer crossed (b jumps and tau kinks
         // at the edges) and, past the last edge, the map r = a - log(1-x)/c
         // that absorbs the exponential attenuation; inner 8 x 8 cap rule.
+        // (K peaks sharply in r along rays that pass close to the sensor: on a
+        // sample of cone targets in a 100-layer medium the 90th-percentile
+        // error against a finer rule was 7.7e-3 with 16 points per piece and
+        // 1.7e-3 with 32; more cap or direction nodes gained less per
+        // evaluation.)
         const int cnt = T.mcnt;
         const double Dn = sqrt(dot(T.eta, T.eta));
         for (int i = threadIdx.x; i < 32 * 32; i += blockDim.x) {
@@ -153,8 +157,8 @@ __global__ void __launch_bounds__(256) anchor_kernel(KArgs a, const double* gx, 
                 const bool tail = !(bnd < 1e299);
                 const LayV<double> ly = lay_at(T, l);
                 const double cm = ly.c, bm = ly.b;
-                for (int q = 0; q < 16; ++q) {
-                    double y = x16[q], wy = w16[q], r, wr;
+                for (int q = 0; q < 32; ++q) {
+                    double y = x32[q], wy = w32[q], r, wr;
                     if (!tail) {
                         r = a + (bnd - a) * y;
                         wr = wy * (bnd - a) * exp(-taua - cm * (r - a));

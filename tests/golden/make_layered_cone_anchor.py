@@ -2,7 +2,12 @@
 (nested product Gauss rules over the emission cone, the ray and the sensor
 cap) for cone-source targets of the 100-layer workload, at three
 resolutions, so that the convergence of the quadrature is on record next to
-the value the device anchor is compared with.  Calls only the oracle."""
+the value the device anchor is compared with; and
+layered_cone_anchor_sample.txt: the same at the two lower resolutions for a
+seeded random sample of that workload's targets with n0 = 3, which puts a
+number on the anchor error across the batch.  Calls only the oracle.
+
+    python make_layered_cone_anchor.py [fixed|sample]   (default: both)"""
 import os
 import sys
 from concurrent.futures import ProcessPoolExecutor
@@ -14,17 +19,51 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 # n0 = 3 among the nearest, whose anchor the device is compared on
 TARGETS = [877, 364, 321]
 RULES = [(24, 24, 16, 10, 10), (40, 40, 24, 12, 12), (56, 56, 32, 16, 16)]
+SAMPLE_SEED, SAMPLE_SIZE = 11, 40
 
 
-def one(t):
-    from oracle import oracle as O
+def _workload():
     from paper_1811_04156_amd import workloads as W
-    w = W.layered_pairs(seed=3, pairs=1000, chains=1000, cap=512)
+    return W.layered_pairs(seed=3, pairs=1000, chains=1000, cap=512)
+
+
+def one(t, rules=RULES):
+    from oracle import oracle as O
+    w = _workload()
     orc = O.Oracle(w)
-    return t, int(w["t_n0"][t]), [orc.anchor_I3(t, *r) for r in RULES]
+    return t, int(w["t_n0"][t]), [orc.anchor_I3(t, *r) for r in rules]
 
 
-if __name__ == "__main__":
+def one_low_mid(t):
+    return one(t, RULES[:2])
+
+
+def sample_targets():
+    """SAMPLE_SIZE targets drawn without replacement (seeded) from those with
+    n0 = 3, the fixed ones left out."""
+    import numpy as np
+    n0 = np.asarray(_workload()["t_n0"])
+    pool = [t for t in np.flatnonzero(n0 == 3).tolist() if t not in TARGETS]
+    rng = np.random.default_rng(SAMPLE_SEED)
+    return sorted(int(t) for t in rng.choice(pool, SAMPLE_SIZE, replace=False))
+
+
+def write_sample():
+    ts = sample_targets()
+    with ProcessPoolExecutor(min(8, os.cpu_count() or 1)) as ex:
+        rows = list(ex.map(one_low_mid, ts))
+    with open(os.path.join(HERE, "layered_cone_anchor_sample.txt"), "w") as f:
+        f.write("# Single-scatter anchor I_3 of a seeded random sample (seed %d, %d targets) of the n0 = 3\n"
+                % (SAMPLE_SEED, SAMPLE_SIZE))
+        f.write("# targets of the 100-layer, 1000-pair workload (seed 3), by the oracle's nested product\n")
+        f.write("# Gauss rules at resolutions " + "; ".join("x".join(map(str, r)) for r in RULES[:2]) + "\n")
+        f.write("# target n0 I3_low I3_mid\n")
+        for t, n0, v in rows:
+            f.write(f"{t} {n0} " + " ".join(f"{x:.15e}" for x in v) + "\n")
+
+
+
+def write_fixed():
     with ProcessPoolExecutor(len(TARGETS)) as ex:
         rows = list(ex.map(one, TARGETS))
     with open(os.path.join(HERE, "layered_cone_anchor.txt"), "w") as f:
@@ -35,3 +74,11 @@ if __name__ == "__main__":
         f.write("# target n0 I3_low I3_mid I3_high\n")
         for t, n0, v in rows:
             f.write(f"{t} {n0} " + " ".join(f"{x:.15e}" for x in v) + "\n")
+
+
+if __name__ == "__main__":
+    which = sys.argv[1] if len(sys.argv) > 1 else "both"
+    if which in ("fixed", "both"):
+        write_fixed()
+    if which in ("sample", "both"):
+        write_sample()
