@@ -5,9 +5,12 @@ resolutions, so that the convergence of the quadrature is on record next to
 the value the device anchor is compared with; and
 layered_cone_anchor_sample.txt: the same at the two lower resolutions for a
 seeded random sample of that workload's targets with n0 = 3, which puts a
-number on the anchor error across the batch.  Calls only the oracle.
+number on the anchor error across the batch; and layered_cone_anchor_rim.txt:
+two finer resolutions for the sampled targets whose sensor lies within a few
+degrees outside the emission cone's rim, where the two lower ones disagree.
+Calls only the oracle.
 
-    python make_layered_cone_anchor.py [fixed|sample]   (default: both)"""
+    python make_layered_cone_anchor.py [fixed|sample|rim]   (default: all)"""
 import os
 import sys
 from concurrent.futures import ProcessPoolExecutor
@@ -20,6 +23,9 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 TARGETS = [877, 364, 321]
 RULES = [(24, 24, 16, 10, 10), (40, 40, 24, 12, 12), (56, 56, 32, 16, 16)]
 SAMPLE_SEED, SAMPLE_SIZE = 11, 40
+# sampled targets with the sensor 0.95 and 3.1 degrees outside the cone's rim
+RIM_TARGETS = [484, 269]
+RIM_RULES = [(56, 56, 32, 16, 16), (64, 64, 48, 12, 12)]
 
 
 def _workload():
@@ -36,6 +42,11 @@ def one(t, rules=RULES):
 
 def one_low_mid(t):
     return one(t, RULES[:2])
+
+
+def one_rim(tr):
+    t, r = tr
+    return t, one(t, [r])[2][0]
 
 
 def sample_targets():
@@ -76,9 +87,24 @@ def write_fixed():
             f.write(f"{t} {n0} " + " ".join(f"{x:.15e}" for x in v) + "\n")
 
 
+def write_rim():
+    jobs = [(t, r) for t in RIM_TARGETS for r in RIM_RULES]
+    with ProcessPoolExecutor(len(jobs)) as ex:
+        vals = list(ex.map(one_rim, jobs))
+    with open(os.path.join(HERE, "layered_cone_anchor_rim.txt"), "w") as f:
+        f.write("# Single-scatter anchor I_3 of sampled targets of the 100-layer, 1000-pair workload (seed 3)\n")
+        f.write("# whose sensor lies just outside the emission cone's rim, by the oracle's nested product\n")
+        f.write("# Gauss rules at resolutions " + "; ".join("x".join(map(str, r)) for r in RIM_RULES) + "\n")
+        f.write("# target I3_fine1 I3_fine2\n")
+        for t in RIM_TARGETS:
+            f.write(f"{t} " + " ".join(f"{v:.15e}" for tt, v in vals if tt == t) + "\n")
+
+
 if __name__ == "__main__":
-    which = sys.argv[1] if len(sys.argv) > 1 else "both"
-    if which in ("fixed", "both"):
+    which = sys.argv[1] if len(sys.argv) > 1 else "all"
+    if which in ("fixed", "all"):
         write_fixed()
-    if which in ("sample", "both"):
+    if which in ("sample", "all"):
         write_sample()
+    if which in ("rim", "all"):
+        write_rim()

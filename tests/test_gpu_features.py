@@ -205,6 +205,18 @@ def test_anchor_over_a_sample_of_layered_cone_targets(rj):
           f"90th percentile {np.quantile(errs, 0.9):.2e}, max {errs.max():.2e}")
     assert conv >= len(gold) // 2
     assert np.quantile(errs, 0.9) < 5e-3
+    # the sampled targets whose sensor lies just outside the cone's rim
+    # (0.95 and 3.1 degrees), against two finer oracle rules
+    # (tests/golden/layered_cone_anchor_rim.txt): within 2e-3 plus their spread
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "layered_cone_anchor_rim.txt")
+    rim = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+    assert len(rim) == 2
+    for r in rim:
+        t, f1, f2 = int(r[0]), float(r[1]), float(r[2])
+        e = an[t] / f2 - 1
+        print(f"rim target {t}: oracle fine1/fine2 - 1 = {f1 / f2 - 1:+.2e}; device/fine2 - 1 = {e:+.2e}")
+        assert abs(e) < 2e-3 + abs(f1 / f2 - 1), (t, an[t], f2)
 
 
 def test_tilt_kernel_follows_its_rule(rj):
