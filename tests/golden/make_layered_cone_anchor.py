@@ -7,10 +7,13 @@ layered_cone_anchor_sample.txt: the same at the two lower resolutions for a
 seeded random sample of that workload's targets with n0 = 3, which puts a
 number on the anchor error across the batch; and layered_cone_anchor_rim.txt:
 two finer resolutions for the sampled targets whose sensor lies within a few
-degrees outside the emission cone's rim, where the two lower ones disagree.
-Calls only the oracle.
+degrees outside the emission cone's rim, where the two lower ones disagree;
+and layered_cone_anchor_devres.txt: the oracle's rule at the resolution the
+device's anchor uses (32 x 32 directions, 64 x 64 within 10 degrees outside
+a cone's rim; 32 radial nodes per layer piece; 8 x 8 cap nodes), to which the
+device's value is held closely.  Calls only the oracle.
 
-    python make_layered_cone_anchor.py [fixed|sample|rim]   (default: all)"""
+    python make_layered_cone_anchor.py [fixed|sample|rim|devres]   (default: all)"""
 import os
 import sys
 from concurrent.futures import ProcessPoolExecutor
@@ -26,6 +29,11 @@ SAMPLE_SEED, SAMPLE_SIZE = 11, 40
 # sampled targets with the sensor 0.95 and 3.1 degrees outside the cone's rim
 RIM_TARGETS = [484, 269]
 RIM_RULES = [(56, 56, 32, 16, 16), (64, 64, 48, 12, 12)]
+# the device's resolution: two targets far from a rim (sensors 173 and 79
+# degrees off the cone's axis), then three within 10 degrees outside it (0.95,
+# 3.1 and 7.9 degrees)
+DEVRES = [(128, (32, 32, 32, 8, 8)), (392, (32, 32, 32, 8, 8)),
+          (484, (64, 64, 32, 8, 8)), (269, (64, 64, 32, 8, 8)), (877, (64, 64, 32, 8, 8))]
 
 
 def _workload():
@@ -100,6 +108,17 @@ def write_rim():
             f.write(f"{t} " + " ".join(f"{v:.15e}" for tt, v in vals if tt == t) + "\n")
 
 
+def write_devres():
+    with ProcessPoolExecutor(len(DEVRES)) as ex:
+        vals = list(ex.map(one_rim, DEVRES))
+    with open(os.path.join(HERE, "layered_cone_anchor_devres.txt"), "w") as f:
+        f.write("# Single-scatter anchor I_3 of targets of the 100-layer, 1000-pair workload (seed 3) by the\n")
+        f.write("# oracle's nested product Gauss rules at the device anchor's resolution\n")
+        f.write("# target n_polar n_azimuth n_radial n_cap_v n_cap_psi I3\n")
+        for (t, r), (_, v) in zip(DEVRES, vals):
+            f.write(f"{t} " + " ".join(map(str, r)) + f" {v:.15e}\n")
+
+
 if __name__ == "__main__":
     which = sys.argv[1] if len(sys.argv) > 1 else "all"
     if which in ("fixed", "all"):
@@ -108,3 +127,5 @@ if __name__ == "__main__":
         write_sample()
     if which in ("rim", "all"):
         write_rim()
+    if which in ("devres", "all"):
+        write_devres()
