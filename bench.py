@@ -213,7 +213,7 @@ def proposal_candidates(w, sampler):
             for npert in (2, 3, 4):
                 add(dict(base, mala_h=h, cycle_len=5, n_perturb=npert))
     else:
-        for sig in (0.5, 1.0, 2.0, 4.0):
+        for sig in (0.5, 1.0, 2.0, 4.0, 8.0, 16.0):
             for npert in (2, 3):
                 add(dict(base, sigma=sig, cycle_len=5, n_perturb=npert))
         for sig in (1.0, 2.0):
