@@ -407,6 +407,8 @@ def grad_vs_plain(h, max_steps, tree_h=0.3, trial=3000):
         out[name] = {"steps": steps, "seconds": sec, "median_rel_err": r, "reached_1pct": r <= 0.01,
                      "proposal": {k: cands[best][k] for k in ("sigma", "kappa_end", "cycle_len", "n_perturb", "mala_h")},
                      "ess_per_s": 1.0 / (r * r * sec), "evals_per_s": evaluated(st) / sec,
+                     # mixing per step (lower is better) and cost per step: ESS/s = 1 / (their product)
+                     "r2_times_steps": r * r * steps, "us_per_step": sec / steps * 1e6,
                      "perturb_acceptance": float(st[:, 9].sum() / max(1.0, st[:, 6].sum())),
                      "mean_vertices": float(st[:, 5].sum() / max(1.0, st[:, 0].sum()))}
     out["ess_ratio_langevin_over_plain"] = out["langevin"]["ess_per_s"] / out["plain"]["ess_per_s"]
