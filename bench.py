@@ -114,6 +114,8 @@ def parse():
                     help="step-size scale of the single-vertex Langevin sampler in the grad-vs-plain leg")
     ap.add_argument("--proposal-trial", type=int, default=3000,
                     help="sampler steps per candidate and pass of the proposal tuner")
+    ap.add_argument("--final-factor", type=int, default=16,
+                    help="trial length of the tuner's second stage, in first-stage trials")
     ap.add_argument("--ess-max-steps", type=int, default=200,
                     help="further benchmark steps allowed after the timed ones to reach 1%% error (ESS/s)")
     ap.add_argument("--gvp-max-steps", type=int, default=1_600_000,
@@ -226,7 +228,7 @@ def proposal_candidates(w, sampler):
     return out
 
 
-def tune_two_stage(s, cands, trial, run=None, top=3, factor=4):
+def tune_two_stage(s, cands, trial, run=None, top=3, factor=16):
     """The proposal tuner in two stages: every candidate on trials of `trial`
     steps, then the `top` best of those again on trials `factor` times as
     long, the pick being the best of the second stage (a short trial's ESS/s
@@ -255,7 +257,7 @@ def layered_headline(args):
     block, vlds = s.autotune(2400)
     if args.n_perturb is None:
         cands = proposal_candidates(w, args.sampler)
-        best, scores, finalists = tune_two_stage(s, cands, args.proposal_trial)
+        best, scores, finalists = tune_two_stage(s, cands, args.proposal_trial, factor=args.final_factor)
         s.w.update(cands[best])
     else:
         # a fixed move mix (profiling one move class): no proposal tuning
@@ -337,7 +339,7 @@ def layered_headline(args):
                    "launch": {"block_chains": block, "v_lds": vlds, "graph": True},
                    "proposal": {k: s.w[k] for k in ("sigma", "kappa_end", "cycle_len", "n_perturb", "mala_h")},
                    "proposal_tuning": {"candidates": len(cands), "trial_steps": args.proposal_trial,
-                                       "finalists": len(finalists), "final_trial_steps": 4 * args.proposal_trial,
+                                       "finalists": len(finalists), "final_trial_steps": args.final_factor * args.proposal_trial,
                                        "best_score_over_default": float(scores[best] / scores[0])}},
         # 1 / (r^2 t) with the error measured where it first reaches 1% (the
         # checks come every 10 benchmark steps after the timed ones)
@@ -380,7 +382,7 @@ def _until_1pct(s, run, chunk, max_steps):
     return done, time.perf_counter() - t0, r
 
 
-def grad_vs_plain(h, max_steps, tree_h=0.3, trial=3000):
+def grad_vs_plain(h, max_steps, tree_h=0.3, trial=3000, factor=16):
     """262,144 chains on the layered batch's medium and cone-source geometry:
     the plain sampler vs the single-vertex Langevin (gradient-informed)
     sampler and the tree-coordinate sampler (a whole-path move on the first
@@ -399,7 +401,7 @@ def grad_vs_plain(h, max_steps, tree_h=0.3, trial=3000):
         run = dict(sampler=samp, mala_h=hh, burn_in=0)
         s.run(3000, run=run)
         cands = proposal_candidates(dict(w, mala_h=hh), name)
-        best, _, _ = tune_two_stage(s, cands, trial, run=run)
+        best, _, _ = tune_two_stage(s, cands, trial, run=run, factor=factor)
         run.update(cands[best])
         steps, sec, r = _until_1pct(s, run, 4000, max_steps)
         progress(f"grad-vs-plain: {name} sampler, {steps} steps, {sec:.1f} s, r = {r:.4f}")
@@ -511,7 +513,7 @@ def main():
         out["homogeneous_batch"] = homogeneous_batch(max_steps=args.hom_max_steps)
         progress("homogeneous batch done")
         out["grad_vs_plain"] = grad_vs_plain(args.lmala_h, args.gvp_max_steps, tree_h=args.tree_h,
-                                             trial=args.proposal_trial)
+                                             trial=args.proposal_trial, factor=args.final_factor)
         progress("grad-vs-plain leg done")
     if args.occupancy_probe:
         out["occupancy_probe"] = occupancy_probe()

@@ -103,7 +103,7 @@ def test_two_stage_tuner_takes_the_best_finalist_of_the_longer_trials():
     f = _FakeTuner(short, long)
     best, sc1, fin = bench.tune_two_stage(f, cands, 100)
     assert fin == [4, 1, 2] and best == 2
-    assert f.calls == [(6, 100), (3, 400)]
+    assert f.calls == [(6, 100), (3, 1600)]
     assert list(sc1) == short
     # fewer candidates than finalists: all of them go through
     f = _FakeTuner(short, long)
