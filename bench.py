@@ -215,11 +215,10 @@ def proposal_candidates(w, sampler):
             for npert in (2, 3, 4):
                 add(dict(base, mala_h=h, cycle_len=5, n_perturb=npert))
     else:
+        # the same mixes as the Langevin grid, crossed with the Gaussian step
         for sig in (0.5, 1.0, 2.0, 4.0, 8.0, 16.0):
-            for npert in (2, 3):
+            for npert in (2, 3, 4):
                 add(dict(base, sigma=sig, cycle_len=5, n_perturb=npert))
-        for sig in (1.0, 2.0):
-            add(dict(base, sigma=sig, cycle_len=5, n_perturb=4))
     for kap in (5.0, 60.0):
         add(dict(base, kappa_end=kap))
     if sampler == "tree":

@@ -50,6 +50,8 @@ def test_proposal_candidates():
     plain = bench.proposal_candidates(w, "plain")
     assert plain[0] == w  # the workload's own proposal first
     assert {c["n_perturb"] for c in plain} == {2, 3, 4}
+    # the plain grid crosses the same mixes with every step size as the Langevin one
+    assert {(c["sigma"], c["n_perturb"]) for c in plain} >= {(s, k) for s in (0.5, 8.0, 16.0) for k in (2, 3, 4)}
     assert all(0 < c["n_perturb"] < c["cycle_len"] for c in plain)  # every mix keeps both move classes
     assert len({tuple(sorted(c.items())) for c in plain}) == len(plain)  # no candidate twice
     lang = bench.proposal_candidates(w, "langevin")
